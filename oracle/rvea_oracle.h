@@ -1,0 +1,78 @@
+/*
+ * rvea_oracle.h -- declarations of the FP64 CPU oracle (test infrastructure
+ * only; see rvea_oracle.c).  This header belongs to the oracle alone: the
+ * HIP library neither includes it nor shares any of its definitions.
+ */
+#ifndef RVEA_ORACLE_H
+#define RVEA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORA_OK 0
+#define ORA_EINVAL (-1)
+#define ORA_ESTATE (-4)
+
+/* Philox stream tags (fourth counter word) */
+#define ORA_TAG_INIT 0u
+#define ORA_TAG_MATE 1u
+#define ORA_TAG_SBX 2u
+#define ORA_TAG_SBXPAIR 3u
+#define ORA_TAG_MUT 4u
+
+typedef struct ora_params {
+    double alpha;  /* APD penalty rate (Eq. 4) */
+    double fr;     /* reference-vector adaptation frequency */
+    int32_t t_max; /* maximal number of generations */
+    int32_t pad_;
+    double eta_c; /* SBX distribution index */
+    double eta_m; /* polynomial-mutation distribution index (xi) */
+    double p_c;   /* crossover probability */
+    double p_m;   /* mutation probability; per-site rate is p_m / d */
+    double lb, ub;
+} ora_params;
+
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+int64_t ora_binomial(int64_t n, int64_t k);
+int64_t ora_lattice_count(int H, int m);
+int64_t ora_lattice(int H, int m, double *W, int64_t cap);
+void ora_normalize_rows(const double *W, int64_t K, int m, double *V);
+void ora_gamma(int64_t K, int m, const double *V, double *gamma);
+int ora_evaluate_one(int problem, int m, int d, const float *x, double *f);
+int ora_evaluate(int problem, int m, int d, int64_t n, const float *X, int64_t ldx, double *F);
+int64_t ora_front(int problem, int m, int Hs, double *Fs, int64_t cap);
+double ora_igd(const double *F, int64_t n, const double *Fs, int64_t ns, int m);
+void ora_init(uint64_t seed, int64_t N, int d, double lb, double ub, float *X, int64_t ldx);
+int64_t ora_mate(uint64_t seed, int64_t t, int64_t K, int64_t N, const uint8_t *valid,
+                 int32_t *parents);
+double ora_sbx_beta(double mc, double eta);
+double ora_pm_delta(double x, double lb, double ub, double mm, double xi);
+int ora_mutation_sites(uint64_t seed, int64_t t, int64_t o, int d, double p_m, int32_t *sites,
+                       double *mags, int cap);
+void ora_mutate_child(uint64_t seed, int64_t t, int64_t o, int d, double p_m, double lb,
+                      double ub, double eta_m, double *c);
+int ora_reproduce(const ora_params *P, uint64_t seed, int64_t t, int64_t K, int64_t N, int d,
+                  const float *X, int64_t ldx, const int32_t *parents, float *Xoff,
+                  int64_t ldo, double *pre);
+int ora_select(int m, int64_t K, int64_t N, int64_t t, int t_max, double alpha, const double *Fm,
+               const uint8_t *mvalid, const double *V, const double *gamma, double *zstar,
+               int32_t *assoc, double *theta, double *apd, int32_t *surv);
+int ora_adapt(int64_t K, int m, const double *V0, const double *F, const uint8_t *valid,
+              double *V);
+int ora_adapt_period(double fr, int t_max);
+int ora_generation(const ora_params *P, int problem, int m, int d, int64_t N, int64_t K,
+                   uint64_t seed, int64_t t, float *X, double *F, uint8_t *valid, double *V,
+                   const double *V0, double *gamma, float *Xoff_out, double *Foff_out,
+                   int32_t *parents_out, int32_t *surv_out, int *adapted);
+int ora_run(const ora_params *P, int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
+            int gens, float *X, double *F, uint8_t *valid, double *V, double *V0, double *gamma);
+int ora_num_threads(void);
+void ora_set_num_threads(int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,74 @@
+"""Seeded synthetic inputs shared by the tests and the benchmark.
+
+This module holds workload shapes and numpy random generators only; it
+contains none of the method's arithmetic, so the HIP path and the CPU oracle
+can both be fed from it without sharing any code with each other.
+
+The paper measures on the DTLZ suite, whose definitions it does not give.
+The problems used here (ids 1..3) are this repository's own stand-ins of the
+same shape (m objectives, d variables in [0,1], m-1 position variables and
+d-m+1 distance variables); the problem id plays the role of the DTLZ
+instance each workload names:
+    1  linear front, multimodal distance term   (in place of DTLZ1)
+    2  sphere front, unimodal distance term     (in place of DTLZ2)
+    3  sphere front, multimodal distance term   (in place of DTLZ3)
+"""
+import numpy as np
+
+LINEAR_MULTIMODAL = 1
+SPHERE_UNIMODAL = 2
+SPHERE_MULTIMODAL = 3
+
+# Workloads of the paper's scale: name -> shape.  K = N = Das-Dennis count.
+CONFIGS = {
+    # 105 reference vectors (H=13, m=3), d=12, 100 generations
+    "small_m3_d12_n105": dict(problem=SPHERE_UNIMODAL, m=3, d=12, H=13, N=105, K=105,
+                              gens=100, seed=0),
+    # headline: H=140 -> K=N=10,011, d=500, 100 generations
+    "large_m3_d500_n10011": dict(problem=LINEAR_MULTIMODAL, m=3, d=500, H=140, N=10011,
+                                 K=10011, gens=100, seed=0),
+    # big population: H=446 -> K=N=100,128, d=5,000, 50 generations
+    "big_m3_d5000_n100128": dict(problem=SPHERE_MULTIMODAL, m=3, d=5000, H=446, N=100128,
+                                 K=100128, gens=50, seed=0),
+}
+
+DEFAULT_PARAMS = dict(alpha=2.0, fr=0.1, t_max=100, eta_c=20.0, eta_m=20.0, p_c=1.0,
+                      p_m=1.0, lb=0.0, ub=1.0)
+
+
+def rng(seed):
+    return np.random.default_rng(np.uint64(seed))
+
+
+def population(seed, K, d, lb=0.0, ub=1.0):
+    """K x d float32 genes uniform in [lb, ub]."""
+    r = rng(seed)
+    return r.uniform(lb, ub, size=(K, d)).astype(np.float32)
+
+
+def valid_mask(seed, K, frac_valid=1.0):
+    """uint8 mask with about frac_valid of the K slots set (at least one)."""
+    r = rng(seed)
+    v = (r.random(K) < frac_valid).astype(np.uint8)
+    if v.sum() == 0:
+        v[r.integers(0, K)] = 1
+    return v
+
+
+def objectives(seed, M, m, radius=(0.5, 2.0), offset=0.0):
+    """M x m float32 objective vectors: positive-orthant directions (|normal|)
+    with radii uniform in ``radius``, shifted by ``offset``."""
+    r = rng(seed)
+    g = np.abs(r.standard_normal((M, m)))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    rad = r.uniform(radius[0], radius[1], size=(M, 1))
+    return (g * rad + offset).astype(np.float32)
+
+
+def gamma_like(seed, K, lo=0.02, hi=0.2):
+    """Positive per-vector angles, for feeding selection in isolation."""
+    return rng(seed).uniform(lo, hi, size=K)
+
+
+def seeds(n, base=0):
+    return [base + i for i in range(n)]
