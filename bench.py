@@ -1,0 +1,163 @@
+"""Benchmark: RVEA generations per second on one MI355X.
+
+One step = one whole generation of the hot path (rvea_step, rvea_select,
+rvea_adapt: mating, SBX + polynomial mutation, evaluation, ideal point,
+association, APD, per-vector argmin, new population, periodic adaptation)
+on the 10,011-vector, d=500, m=3 workload (linear-front multimodal test
+problem, N = K = 10,011).  Everything is resident in HBM before timing
+starts.  Prints one JSON line.
+
+Also reported, for the kernel that takes the most time: its roofline
+(algorithmic bytes or flops per launch over its HIP-event-timed average
+launch), and the CPU oracle timed on a bounded sample of generations of the
+same workload on the host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed); 78.6 without packed FP32
+WORKLOAD = "large_m3_d500_n10011"
+
+
+def kernel_work(name, run):
+    """Algorithmic work of one launch: (unit, amount)."""
+    N, K, d, m = run.N, run.K, run.d, run.m
+    P = (N + 1) // 2
+    if name == "offspring":
+        # read both parent rows of every pair, write every child row and its objectives
+        return "bytes", 2 * P * d * 4 + N * d * 4 + N * m * 4
+    if name == "assoc":
+        # every (merged row, vector) pair: m multiplies, m-1 adds, 1 max
+        return "flops", (K + N) * K * 2 * m
+    if name == "rerank":
+        return "bytes", (K + N) * (m * 4 + 8 + 4)
+    return "bytes", 0
+
+
+def cpu_baseline(cfg, budget_s):
+    import oracle as O
+
+    prm = O.params()
+    st = O.initial_state(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], cfg["seed"])
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        O.generation(prm, cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], cfg["seed"],
+                     n + 1, st)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= cfg["gens"]:
+            break
+    return dict(value=n / el, unit="generations/s", cores=O.num_threads(), kind="oracle",
+                sample=f"generations 1..{n} of the same workload from its initial state, "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default=WORKLOAD)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="skip the per-kernel events (for profiler runs)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {a.gpus} is not supported by this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2404_01159_amd as P
+    from workloads import CONFIGS
+
+    cfg = CONFIGS[a.config]
+    prm = P.default_params(t_max=max(cfg["gens"], 1))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # warm-up on a separate run of the same shape
+    warm = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"] + 1,
+                 params=prm, device="cuda:0")
+    warm.run(a.warmup)
+    warm.synchronize()
+    warm.close()
+    del warm
+
+    run = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"],
+                params=prm, device="cuda:0")
+    names = ["offspring", "assoc", "rerank", "adapt"]
+    if not a.no_timing:
+        run.set_timing([0, 1, 2])
+    run.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.run(a.steps)
+    run.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gens_per_s = a.steps / el
+
+    roof = None
+    per_kernel = {}
+    if not a.no_timing:
+        for k in range(3):
+            ms, n = run.kernel_time(k)
+            if n:
+                per_kernel[names[k]] = (ms / n, n)
+        dom = max(per_kernel, key=lambda k: per_kernel[k][0] * per_kernel[k][1])
+        avg_ms, n = per_kernel[dom]
+        unit, work = kernel_work(dom, run)
+        if unit == "bytes":
+            ach = work / (avg_ms * 1e-3) / 1e9
+            roof = dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s",
+                        frac=ach / PEAK_HBM_GBS, traffic=None, kernel=dom,
+                        avg_launch_us=avg_ms * 1e3, launches=n)
+        else:
+            ach = work / (avg_ms * 1e-3) / 1e12
+            roof = dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                        frac=ach / PEAK_FP32_TFLOPS, traffic=None, kernel=dom,
+                        avg_launch_us=avg_ms * 1e3, launches=n)
+    st = run.get_state(genes=False)
+    run.close()
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, a.cpu_budget)
+
+    out = {
+        "metric": "RVEA generations/s at N=10k,m=3,d=500 vs plain",
+        "value": gens_per_s,
+        "unit": "generations/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": el * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 genes and objectives, f64 selection finish",
+        "data": "synthetic",
+        "config": {"workload": a.config, "problem": "linear front, multimodal distance term",
+                   "N": cfg["N"], "K": cfg["K"], "m": cfg["m"], "d": cfg["d"],
+                   "generations_timed": a.steps, "survivors_final": int(st["valid"].sum())},
+        "roofline": roof,
+        "kernels_avg_us": {k: v[0] * 1e3 for k, v in per_kernel.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

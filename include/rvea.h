@@ -1,0 +1,186 @@
+/*
+ * rvea.h -- C ABI of the MI355X TensorRVEA generation library (librvea.so).
+ *
+ * The library runs one generation of the reference-vector guided
+ * evolutionary algorithm as tensorized by Liang, Jiang, Sun and Cheng,
+ * "GPU-accelerated Evolutionary Multiobjective Optimization Using
+ * Tensorized RVEA" (GECCO'24), on one AMD Instinct MI355X (gfx950):
+ *   rvea_step   -- random mating, SBX crossover and polynomial mutation
+ *                  (Appendix B), evaluation of the offspring;
+ *   rvea_select -- translation by the ideal point, association of the
+ *                  merged population to the reference vectors, angle-
+ *                  penalized distance, per-vector argmin (Alg. 1,
+ *                  Eqs. 2-5), new population;
+ *   rvea_adapt  -- reference-vector update of Alg. 2.
+ * The problem statement it serves is Eq. 1 (minimise f(x) in R^m over
+ * x in R^d).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an rvea_status; nothing throws across the ABI.
+ *   - Device memory is owned by the caller.  rvea_create receives one
+ *     device workspace of at least rvea_footprint() bytes and never
+ *     allocates device memory itself; the workspace must stay alive and
+ *     untouched by the caller until rvea_destroy.  Host pointers passed to
+ *     the state accessors are read or written before the call returns.
+ *   - Work is enqueued asynchronously on the HIP stream given to
+ *     rvea_create (NULL = the default stream); rvea_synchronize or any
+ *     accessor that returns data waits for it.
+ *   - A run handle is not thread safe; distinct handles are independent.
+ *   - Call order per generation: rvea_step, rvea_select, rvea_adapt.
+ *     A call out of this order returns RVEA_ESTATE and enqueues nothing.
+ *   - On RVEA_EDEVICE the HIP error text is available from
+ *     rvea_last_error(run).
+ */
+#ifndef RVEA_H
+#define RVEA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rvea_status {
+    RVEA_OK = 0,
+    RVEA_EINVAL = -1,      /* an argument is out of range */
+    RVEA_ENOMEM = -2,      /* workspace smaller than rvea_footprint() */
+    RVEA_EDEVICE = -3,     /* a HIP call failed; see rvea_last_error */
+    RVEA_ESTATE = -4,      /* call out of order, or no valid individual left */
+    RVEA_EUNSUPPORTED = -5 /* a configuration this build does not run */
+} rvea_status;
+
+/* Test problems.  The paper benchmarks on DTLZ, which it does not define;
+ * these are the library's own problems of the same shape on [0,1]^d: the
+ * first m-1 variables place a point w on the simplex (uniform spacings of
+ * the sorted variables), the remaining k = d-m+1 set a distance term g >= 0
+ * that is 0 when all of them equal 1/2.
+ *   LINEAR_MULTIMODAL : f = (1+g) w,          g = mean(10 t^2 + 2 sin^2(4 pi t))
+ *   SPHERE_UNIMODAL   : f = (1+g) w / |w|,    g = 4 mean(t^2)
+ *   SPHERE_MULTIMODAL : f = (1+g) w / |w|,    g as LINEAR_MULTIMODAL
+ * with t = x - 1/2 over the distance variables. */
+typedef enum rvea_problem {
+    RVEA_LINEAR_MULTIMODAL = 1,
+    RVEA_SPHERE_UNIMODAL = 2,
+    RVEA_SPHERE_MULTIMODAL = 3
+} rvea_problem;
+
+/* Algorithm parameters (defaults from rvea_default_params in brackets). */
+typedef struct rvea_params {
+    double alpha;     /* APD penalty rate of Eq. 4 [2] */
+    double fr;        /* adaptation every ceil(fr * t_max) generations [0.1] */
+    int32_t t_max;    /* maximal number of generations, Eq. 4 [100] */
+    int32_t reserved; /* must be 0 */
+    double eta_c;     /* SBX distribution index eta, Appendix B [20] */
+    double eta_m;     /* polynomial-mutation distribution index xi [20] */
+    double p_c;       /* crossover probability [1] */
+    double p_m;       /* mutation probability; per-gene rate p_m/d, 0..4 [1] */
+    double lb, ub;    /* box of every decision variable, lb < ub [0, 1] */
+} rvea_params;
+
+typedef struct rvea_run_s *rvea_run;
+
+/* Fills *out with the defaults above. */
+rvea_status rvea_default_params(rvea_params *out);
+
+/* Reference-vector lattice (Alg. 2 input V_0): K = C(H+m-1, m-1) unit
+ * vectors of the Das-Dennis simplex lattice with H divisions.  Writes the
+ * H with that count for (m, K) to *H, or returns RVEA_EINVAL. */
+rvea_status rvea_lattice_divisions(int m, int64_t K, int *H);
+
+/* Device bytes a run of this shape needs (workspace size for rvea_create).
+ * m in [2,8], d >= m, 1 <= N <= K, K a lattice count for m. */
+rvea_status rvea_footprint(int problem, int m, int d, int64_t N, int64_t K,
+                           const rvea_params *params, size_t *bytes);
+
+/* Creates a run on the current HIP device and enqueues its initialization
+ * (Alg. 2, line 3: N individuals uniform in [lb,ub]^d in slots 0..N-1, the
+ * rest of the K slots empty; V = V_0; gamma of Eq. 5).
+ *   workspace        device pointer, 256-byte aligned, >= footprint bytes
+ *   hip_stream       hipStream_t (may be NULL)
+ *   seed             key of the run's Philox4x32-10 streams
+ *   params           NULL for the defaults; copied */
+rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
+                        const rvea_params *params, void *workspace, size_t workspace_bytes,
+                        void *hip_stream, rvea_run *out);
+
+/* Alg. 2 line 5 and Appendix B for generation t = completed + 1: draws the
+ * N offspring by random mating, SBX and polynomial mutation from the
+ * current population, and evaluates them (Eq. 1). */
+rvea_status rvea_step(rvea_run run);
+
+/* Alg. 2 lines 6-7 / Alg. 1: selects at most one survivor per reference
+ * vector from the K parent slots and the N offspring, writes the new
+ * population into the slots and counts the generation as completed. */
+rvea_status rvea_select(rvea_run run);
+
+/* Alg. 2 line 8: when the completed generation count is a multiple of
+ * ceil(fr * t_max), updates V from V_0 and the survivors' objective ranges
+ * and recomputes gamma; otherwise does nothing. */
+rvea_status rvea_adapt(rvea_run run);
+
+/* n x (rvea_step, rvea_select, rvea_adapt). */
+rvea_status rvea_run_generations(rvea_run run, int n);
+
+/* Copies the run state to host memory (waits for the stream).  Any pointer
+ * may be NULL.  Layouts, row-major: X K x d float, F K x m float,
+ * valid K bytes (1 = slot holds an individual), V and V0 K x m double,
+ * gamma K double; *t = completed generations.  Empty slots hold NaN in F. */
+rvea_status rvea_get_state(rvea_run run, float *X, float *F, uint8_t *valid, double *V,
+                           double *V0, double *gamma, int64_t *t);
+
+/* Replaces the run state from host memory (same layouts; V0 stays the
+ * lattice).  X, F and valid are required; V and gamma may be NULL to keep
+ * the current ones.  Only allowed between generations. */
+rvea_status rvea_set_state(rvea_run run, const float *X, const float *F,
+                           const uint8_t *valid, const double *V, const double *gamma,
+                           int64_t t);
+
+/* After rvea_step, before rvea_select: the offspring X (N x d float), their
+ * objectives F (N x m float) and the mating pairs (ceil(N/2) x 2 slot
+ * indices).  Any pointer may be NULL.  Waits for the stream. */
+rvea_status rvea_get_offspring(rvea_run run, float *X, float *F, int32_t *parents);
+
+/* After rvea_select: the ideal point (m float), the association of each
+ * merged row (K+N int32, -1 for rows that did not take part), its APD
+ * (K+N double, +inf when not taking part) and the survivor of each vector
+ * (K int32 merged-row index, -1 if none).  Waits for the stream. */
+rvea_status rvea_get_selection(rvea_run run, float *zstar, int32_t *assoc, double *apd,
+                               int32_t *surv);
+
+/* Selected rows only: idx[0..n) are slot indices (offspring = 0) or
+ * offspring indices (offspring = 1); writes their genes (n x d float) and
+ * objectives (n x m float).  Either output may be NULL.  Valid between
+ * generations (slots) or after rvea_step until the next rvea_step
+ * (offspring).  Waits for the stream. */
+rvea_status rvea_get_rows(rvea_run run, int offspring, const int64_t *idx, int64_t n, float *X,
+                          float *F);
+
+/* Counters since creation: rows dropped as non-finite, individuals whose
+ * association needed the full double-precision scan. */
+typedef struct rvea_counters {
+    int64_t nonfinite_rows;
+    int64_t full_rescans;
+    int64_t generations;
+} rvea_counters;
+rvea_status rvea_get_counters(rvea_run run, rvea_counters *out);
+
+/* Per-kernel timing with HIP events recorded on the run's stream around the
+ * selected kernels.  Kernel ids: 0 reproduce+evaluate, 1 association,
+ * 2 re-rank+APD, 3 adaptation (vectors + gamma); kernel_mask bit k enables
+ * id k, 0 disables timing.  rvea_kernel_time returns the summed
+ * milliseconds and launch count since timing was last set (waits for the
+ * stream). */
+rvea_status rvea_set_timing(rvea_run run, int kernel_mask);
+rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *launches);
+
+rvea_status rvea_synchronize(rvea_run run);
+rvea_status rvea_destroy(rvea_run run);
+
+const char *rvea_status_str(rvea_status s);
+const char *rvea_last_error(rvea_run run);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -64,12 +64,16 @@ def lib():
             "ora_front": (i64, [i32, i32, i32, P, i64]),
             "ora_igd": (f64, [P, i64, P, i64, i32]),
             "ora_init": (None, [u64, i64, i32, f64, f64, P, i64]),
+            "ora_init_rows": (None, [u64, P, i64, i32, f64, f64, P]),
             "ora_mate": (i64, [u64, i64, i64, i64, P, P]),
             "ora_sbx_beta": (f64, [f64, f64]),
             "ora_pm_delta": (f64, [f64, f64, f64, f64, f64]),
             "ora_mutation_sites": (i32, [u64, i64, i64, i32, f64, P, P, i32]),
             "ora_mutate_child": (None, [u64, i64, i64, i32, f64, f64, f64, f64, P]),
             "ora_reproduce": (i32, [P, u64, i64, i64, i64, i32, P, i64, P, P, i64, P]),
+            "ora_gamma_rows": (None, [i64, i32, P, P, i64, P]),
+            "ora_reproduce_pairs": (i32, [P, u64, i64, i64, i32, P, i64, P, P, i64, P, P]),
+            "ora_assoc_rows": (None, [i32, i64, i64, i32, f64, P, i64, P, P, P, P, P, P]),
             "ora_select": (i32, [i32, i64, i64, i64, i32, f64, P, P, P, P, P, P, P, P, P]),
             "ora_adapt": (i32, [i64, i32, P, P, P, P]),
             "ora_adapt_period": (i32, [f64, i32]),
@@ -187,6 +191,13 @@ def init(seed, N, d, lb=0.0, ub=1.0):
     return X
 
 
+def init_rows(seed, rows, d, lb=0.0, ub=1.0):
+    rows = _c(rows, np.int64)
+    X = np.zeros((len(rows), d), np.float32)
+    lib().ora_init_rows(seed, _p(rows), len(rows), d, lb, ub, _p(X))
+    return X
+
+
 def mate(seed, t, valid, N):
     valid = _c(valid, np.uint8)
     P = (N + 1) // 2
@@ -229,6 +240,42 @@ def reproduce(prm, seed, t, X, parents, N, with_pre=False):
     if rc != 0:
         raise ValueError("ora_reproduce failed")
     return (Xoff, pre) if with_pre else Xoff
+
+
+def gamma_rows(V, rows):
+    V = _c(V, np.float64)
+    rows = _c(rows, np.int64)
+    out = np.zeros(len(rows), np.float64)
+    lib().ora_gamma_rows(V.shape[0], V.shape[1], _p(V), _p(rows), len(rows), _p(out))
+    return out
+
+
+def reproduce_pairs(prm, seed, t, X, parents, N, pairs):
+    """Both children of the listed pair indices: (child1, child2), each n x d."""
+    X = _c(X, np.float32)
+    parents = _c(parents, np.int32)
+    pairs = _c(pairs, np.int64)
+    d = X.shape[1]
+    o1 = np.zeros((len(pairs), d), np.float32)
+    o2 = np.full((len(pairs), d), np.nan, np.float32)
+    lib().ora_reproduce_pairs(C.byref(prm), seed, t, N, d, _p(X), d, _p(parents), _p(pairs),
+                              len(pairs), _p(o1), _p(o2))
+    return o1, o2
+
+
+def assoc_rows(m, K, t, t_max, alpha, Frows, zstar, V, gam):
+    """Association, angle and APD of the given objective rows (ideal point given)."""
+    Frows = _c(Frows, np.float64)
+    zstar = _c(zstar, np.float64)
+    V = _c(V, np.float64)
+    gam = _c(gam, np.float64)
+    n = Frows.shape[0]
+    assoc = np.zeros(n, np.int32)
+    theta = np.zeros(n, np.float64)
+    apd = np.zeros(n, np.float64)
+    lib().ora_assoc_rows(m, K, t, t_max, alpha, _p(Frows), n, _p(zstar), _p(V), _p(gam),
+                         _p(assoc), _p(theta), _p(apd))
+    return assoc, theta, apd
 
 
 def select(m, K, N, t, t_max, alpha, Fm, mvalid, V, gam):

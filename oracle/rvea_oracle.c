@@ -184,26 +184,35 @@ void ora_normalize_rows(const double *W, int64_t K, int m, double *V)
 /* Eq. 5 denotes the angle.  Exactly parallel vectors (cosine >= 1) are     */
 /* skipped; with no other vector gamma = pi/2.                              */
 /* ------------------------------------------------------------------------ */
-void ora_gamma(int64_t K, int m, const double *V, double *gamma)
+static double gamma_one(int64_t K, int m, const double *V, const double *vn, int64_t j)
+{
+    double best = -2.0;
+    int found = 0;
+    for (int64_t i = 0; i < K; ++i) {
+        if (i == j) continue;
+        const double c = dotm(V + i * m, V + j * m, m) / (vn[i] * vn[j]);
+        if (c >= 1.0) continue;
+        if (!found || c > best) {
+            best = c;
+            found = 1;
+        }
+    }
+    return found ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
+}
+
+void ora_gamma_rows(int64_t K, int m, const double *V, const int64_t *rows, int64_t n,
+                    double *out)
 {
     double *vn = (double *)malloc(sizeof(double) * (size_t)K);
     for (int64_t j = 0; j < K; ++j) vn[j] = sqrt(sqnorm(V + j * m, m));
-#pragma omp parallel for schedule(static)
-    for (int64_t j = 0; j < K; ++j) {
-        double best = -2.0;
-        int found = 0;
-        for (int64_t i = 0; i < K; ++i) {
-            if (i == j) continue;
-            const double c = dotm(V + i * m, V + j * m, m) / (vn[i] * vn[j]);
-            if (c >= 1.0) continue;
-            if (!found || c > best) {
-                best = c;
-                found = 1;
-            }
-        }
-        gamma[j] = found ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
-    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n; ++q) out[q] = gamma_one(K, m, V, vn, rows ? rows[q] : q);
     free(vn);
+}
+
+void ora_gamma(int64_t K, int m, const double *V, double *gamma)
+{
+    ora_gamma_rows(K, m, V, NULL, K, gamma);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -307,19 +316,30 @@ double ora_igd(const double *F, int64_t n, const double *Fs, int64_t ns, int m)
 /* Reading: uniform in [lb, ub]; slots 0..N-1 valid, N..K-1 empty.          */
 /* gene g of slot i: Philox counter (g/4, i, 0, TAG_INIT), word g%4.        */
 /* ------------------------------------------------------------------------ */
+static void init_row(uint64_t seed, int64_t i, int d, double lb, double ub, float *x)
+{
+    for (int g = 0; g < d; ++g) {
+        uint32_t w[4];
+        draw(seed, (uint32_t)(g / 4), (uint32_t)i, 0u, ORA_TAG_INIT, w);
+        const double u = u24(w[g % 4]);
+        const double span = ub - lb;
+        const double scaled = span * u;
+        x[g] = (float)(lb + scaled);
+    }
+}
+
 void ora_init(uint64_t seed, int64_t N, int d, double lb, double ub, float *X, int64_t ldx)
 {
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < N; ++i) {
-        for (int g = 0; g < d; ++g) {
-            uint32_t w[4];
-            draw(seed, (uint32_t)(g / 4), (uint32_t)i, 0u, ORA_TAG_INIT, w);
-            const double u = u24(w[g % 4]);
-            const double span = ub - lb;
-            const double scaled = span * u;
-            X[i * ldx + g] = (float)(lb + scaled);
-        }
-    }
+    for (int64_t i = 0; i < N; ++i) init_row(seed, i, d, lb, ub, X + i * ldx);
+}
+
+/* initial genes of the listed slots only (n x d) */
+void ora_init_rows(uint64_t seed, const int64_t *rows, int64_t n, int d, double lb, double ub,
+                   float *X)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) init_row(seed, rows[q], d, lb, ub, X + q * (int64_t)d);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -458,51 +478,84 @@ void ora_mutate_child(uint64_t seed, int64_t t, int64_t o, int d, double p_m, do
     }
 }
 
+/* children of pair p (Appendix B), clipped, mutated, before rounding */
+static void pair_children(const ora_params *P, uint64_t seed, int64_t t, int64_t N, int d,
+                          const float *x1, const float *x2, int64_t p, double *c1, double *c2)
+{
+    const int64_t Pp = (N + 1) / 2;
+    const double lb = P->lb, ub = P->ub;
+    int nocross = 0;
+    if (P->p_c < 1.0) {
+        uint32_t w[4];
+        draw(seed, 0u, (uint32_t)p, (uint32_t)t, ORA_TAG_SBXPAIR, w);
+        nocross = ((double)w[0] * 0x1p-32) > P->p_c;
+    }
+    for (int g = 0; g < d; ++g) {
+        uint32_t w[4];
+        draw(seed, (uint32_t)(g / 4), (uint32_t)p, (uint32_t)t, ORA_TAG_SBX, w);
+        const uint32_t word = w[g % 4];
+        const double mc = u24(word);
+        const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
+        const int r2_high = (int)((word >> 6) & 1u);
+        double B = sgn * ora_sbx_beta(mc, P->eta_c);
+        if (r2_high || nocross) B = 1.0;
+        const double a = (double)x1[g], b = (double)x2[g];
+        const double up = 1.0 + B, dn = 1.0 - B;
+        const double v1 = (up * a + dn * b) / 2.0;
+        const double v2 = (dn * a + up * b) / 2.0;
+        c1[g] = clipd(v1, lb, ub);
+        c2[g] = clipd(v2, lb, ub);
+    }
+    if (p < N) ora_mutate_child(seed, t, p, d, P->p_m, lb, ub, P->eta_m, c1);
+    if (p + Pp < N) ora_mutate_child(seed, t, p + Pp, d, P->p_m, lb, ub, P->eta_m, c2);
+}
+
 int ora_reproduce(const ora_params *P, uint64_t seed, int64_t t, int64_t K, int64_t N, int d,
                   const float *X, int64_t ldx, const int32_t *parents, float *Xoff,
                   int64_t ldo, double *pre)
 {
     (void)K;
     const int64_t Pp = (N + 1) / 2;
-    const double lb = P->lb, ub = P->ub;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < Pp; ++p) {
-        const float *x1 = X + (int64_t)parents[2 * p] * ldx;
-        const float *x2 = X + (int64_t)parents[2 * p + 1] * ldx;
-        int nocross = 0;
-        if (P->p_c < 1.0) {
-            uint32_t w[4];
-            draw(seed, 0u, (uint32_t)p, (uint32_t)t, ORA_TAG_SBXPAIR, w);
-            nocross = ((double)w[0] * 0x1p-32) > P->p_c;
-        }
-        const int64_t o1 = p, o2 = p + Pp;
         double *c1 = (double *)malloc(sizeof(double) * (size_t)d);
         double *c2 = (double *)malloc(sizeof(double) * (size_t)d);
-        for (int g = 0; g < d; ++g) {
-            uint32_t w[4];
-            draw(seed, (uint32_t)(g / 4), (uint32_t)p, (uint32_t)t, ORA_TAG_SBX, w);
-            const uint32_t word = w[g % 4];
-            const double mc = u24(word);
-            const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
-            const int r2_high = (int)((word >> 6) & 1u);
-            double B = sgn * ora_sbx_beta(mc, P->eta_c);
-            if (r2_high || nocross) B = 1.0;
-            const double a = (double)x1[g], b = (double)x2[g];
-            const double up = 1.0 + B, dn = 1.0 - B;
-            const double v1 = (up * a + dn * b) / 2.0;
-            const double v2 = (dn * a + up * b) / 2.0;
-            c1[g] = clipd(v1, lb, ub);
-            c2[g] = clipd(v2, lb, ub);
-        }
+        pair_children(P, seed, t, N, d, X + (int64_t)parents[2 * p] * ldx,
+                      X + (int64_t)parents[2 * p + 1] * ldx, p, c1, c2);
         for (int which = 0; which < 2; ++which) {
-            const int64_t o = which ? o2 : o1;
+            const int64_t o = which ? p + Pp : p;
             if (o >= N) continue;
-            double *c = which ? c2 : c1;
-            ora_mutate_child(seed, t, o, d, P->p_m, lb, ub, P->eta_m, c);
+            const double *c = which ? c2 : c1;
             for (int g = 0; g < d; ++g) {
                 Xoff[o * ldo + g] = (float)c[g];
                 if (pre) pre[o * (int64_t)d + g] = c[g];
             }
+        }
+        free(c1);
+        free(c2);
+    }
+    return ORA_OK;
+}
+
+/* Children of the listed pairs only (pairs[q] indexes the full pair list);
+ * out1/out2 receive the two children of each listed pair (n x d); a child
+ * index >= N is left untouched. */
+int ora_reproduce_pairs(const ora_params *P, uint64_t seed, int64_t t, int64_t N, int d,
+                        const float *X, int64_t ldx, const int32_t *parents, const int64_t *pairs,
+                        int64_t n, float *out1, float *out2)
+{
+    const int64_t Pp = (N + 1) / 2;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t p = pairs[q];
+        if (p < 0 || p >= Pp) continue;
+        double *c1 = (double *)malloc(sizeof(double) * (size_t)d);
+        double *c2 = (double *)malloc(sizeof(double) * (size_t)d);
+        pair_children(P, seed, t, N, d, X + (int64_t)parents[2 * p] * ldx,
+                      X + (int64_t)parents[2 * p + 1] * ldx, p, c1, c2);
+        for (int g = 0; g < d; ++g) {
+            out1[q * (int64_t)d + g] = (float)c1[g];
+            if (p + Pp < N) out2[q * (int64_t)d + g] = (float)c2[g];
         }
         free(c1);
         free(c2);
@@ -525,6 +578,54 @@ int ora_reproduce(const ora_params *P, uint64_t seed, int64_t t, int64_t K, int6
 /* Readings: t is the 1-based generation of this selection; the -1 mask of  */
 /* line 14 is the partition tensor's (an APD entry is never -1).           */
 /* ------------------------------------------------------------------------ */
+/* association, angle and APD of one objective row (Eq. 2, Eq. 4) */
+static void assoc_one(int m, int64_t K, const double *Fi, const double *zstar, const double *V,
+                      const double *vn, const double *gamma, double pen, int32_t *assoc,
+                      double *theta, double *apd)
+{
+    double f[64] = {0};
+    for (int k = 0; k < m; ++k) f[k] = Fi[k] - zstar[k];
+    const double nrm = sqrt(sqnorm(f, m));
+    int64_t best = 0;
+    double bestc = -INFINITY;
+    if (nrm > 0.0) {
+        for (int64_t j = 0; j < K; ++j) {
+            const double c = dotm(f, V + j * m, m) / (nrm * vn[j]);
+            if (c > bestc) {
+                bestc = c;
+                best = j;
+            }
+        }
+    }
+    double th;
+    if (nrm > 0.0) {
+        double c = bestc;
+        if (c > 1.0) c = 1.0;
+        if (c < -1.0) c = -1.0;
+        th = acos(c);
+    } else {
+        th = 1.5707963267948966;
+    }
+    *assoc = (int32_t)best;
+    *theta = th;
+    *apd = (1.0 + pen * th / gamma[best]) * nrm;
+}
+
+/* the same for selected rows, given the ideal point (for sampled checks of
+ * populations too large for the full selection) */
+void ora_assoc_rows(int m, int64_t K, int64_t t, int t_max, double alpha, const double *Frows,
+                    int64_t n, const double *zstar, const double *V, const double *gamma,
+                    int32_t *assoc, double *theta, double *apd)
+{
+    double *vn = (double *)malloc(sizeof(double) * (size_t)K);
+    for (int64_t j = 0; j < K; ++j) vn[j] = sqrt(sqnorm(V + j * m, m));
+    const double pen = (double)m * pow((double)t / (double)t_max, alpha);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n; ++q)
+        assoc_one(m, K, Frows + q * m, zstar, V, vn, gamma, pen, assoc + q, theta + q, apd + q);
+    free(vn);
+}
+
 int ora_select(int m, int64_t K, int64_t N, int64_t t, int t_max, double alpha, const double *Fm,
                const uint8_t *mvalid, const double *V, const double *gamma, double *zstar,
                int32_t *assoc, double *theta, double *apd, int32_t *surv)
@@ -553,32 +654,7 @@ int ora_select(int m, int64_t K, int64_t N, int64_t t, int t_max, double alpha, 
             apd[i] = INFINITY;
             continue;
         }
-        double f[64] = {0};
-        for (int k = 0; k < m; ++k) f[k] = Fm[i * m + k] - zstar[k];
-        const double nrm = sqrt(sqnorm(f, m));
-        int64_t best = 0;
-        double bestc = -INFINITY;
-        if (nrm > 0.0) {
-            for (int64_t j = 0; j < K; ++j) {
-                const double c = dotm(f, V + j * m, m) / (nrm * vn[j]);
-                if (c > bestc) {
-                    bestc = c;
-                    best = j;
-                }
-            }
-        }
-        double th;
-        if (nrm > 0.0) {
-            double c = bestc;
-            if (c > 1.0) c = 1.0;
-            if (c < -1.0) c = -1.0;
-            th = acos(c);
-        } else {
-            th = 1.5707963267948966;
-        }
-        assoc[i] = (int32_t)best;
-        theta[i] = th;
-        apd[i] = (1.0 + pen * th / gamma[best]) * nrm;
+        assoc_one(m, K, Fm + i * m, zstar, V, vn, gamma, pen, assoc + i, theta + i, apd + i);
     }
 
     for (int64_t j = 0; j < K; ++j) surv[j] = -1;

@@ -41,11 +41,15 @@ int64_t ora_lattice_count(int H, int m);
 int64_t ora_lattice(int H, int m, double *W, int64_t cap);
 void ora_normalize_rows(const double *W, int64_t K, int m, double *V);
 void ora_gamma(int64_t K, int m, const double *V, double *gamma);
+void ora_gamma_rows(int64_t K, int m, const double *V, const int64_t *rows, int64_t n,
+                    double *out);
 int ora_evaluate_one(int problem, int m, int d, const float *x, double *f);
 int ora_evaluate(int problem, int m, int d, int64_t n, const float *X, int64_t ldx, double *F);
 int64_t ora_front(int problem, int m, int Hs, double *Fs, int64_t cap);
 double ora_igd(const double *F, int64_t n, const double *Fs, int64_t ns, int m);
 void ora_init(uint64_t seed, int64_t N, int d, double lb, double ub, float *X, int64_t ldx);
+void ora_init_rows(uint64_t seed, const int64_t *rows, int64_t n, int d, double lb, double ub,
+                   float *X);
 int64_t ora_mate(uint64_t seed, int64_t t, int64_t K, int64_t N, const uint8_t *valid,
                  int32_t *parents);
 double ora_sbx_beta(double mc, double eta);
@@ -57,6 +61,12 @@ void ora_mutate_child(uint64_t seed, int64_t t, int64_t o, int d, double p_m, do
 int ora_reproduce(const ora_params *P, uint64_t seed, int64_t t, int64_t K, int64_t N, int d,
                   const float *X, int64_t ldx, const int32_t *parents, float *Xoff,
                   int64_t ldo, double *pre);
+int ora_reproduce_pairs(const ora_params *P, uint64_t seed, int64_t t, int64_t N, int d,
+                        const float *X, int64_t ldx, const int32_t *parents, const int64_t *pairs,
+                        int64_t n, float *out1, float *out2);
+void ora_assoc_rows(int m, int64_t K, int64_t t, int t_max, double alpha, const double *Frows,
+                    int64_t n, const double *zstar, const double *V, const double *gamma,
+                    int32_t *assoc, double *theta, double *apd);
 int ora_select(int m, int64_t K, int64_t N, int64_t t, int t_max, double alpha, const double *Fm,
                const uint8_t *mvalid, const double *V, const double *gamma, double *zstar,
                int32_t *assoc, double *theta, double *apd, int32_t *surv);

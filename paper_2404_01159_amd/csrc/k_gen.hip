@@ -1,0 +1,430 @@
+// k_gen.hip -- population-side kernels: initialization (Alg. 2 line 3),
+// per-generation bookkeeping of valid slots and free gene rows, and the
+// fused offspring kernel (random mating, SBX, polynomial mutation of
+// Appendix B, evaluation of Eq. 1).
+//
+// Layout: genes live in a pool of K+N physical rows of ld floats (ld a
+// multiple of 32, rows 128-byte aligned).  slot_row maps each of the K
+// population slots to its row; survivors are never copied, offspring are
+// written into rows no slot references.
+//
+// The offspring kernel streams each parent pair once: a segment of S lanes
+// (S = 4..64, one wave at most) owns a pair, each lane handles one quad of
+// 4 consecutive genes per step (16-byte loads and stores, one Philox call per
+// quad giving the 4 genes' SBX variates), and the children's distance terms
+// are summed on the fly so evaluation costs no extra pass over the genes.
+#include "rvea_dev.h"
+#include "rvea_problems.h"
+#include "rvea_internal.h"
+
+namespace rvea {
+
+// ------------------------------------------------------------------ scans
+// exclusive prefix sum over a 1024-thread block; returns the element's
+// offset and writes the block total to *total (every thread)
+__device__ int block_scan_1024(int v, int *total)
+{
+    __shared__ int wsum[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int s = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(s, o, 64);
+            if (lane >= o) s += y;
+        }
+        if (lane < 16) wsum[lane] = s;  // inclusive
+    }
+    __syncthreads();
+    const int before = wid > 0 ? wsum[wid - 1] : 0;
+    *total = wsum[15];
+    __syncthreads();
+    return before + x - v;
+}
+
+// One block of 1024 threads: list the valid slots in ascending order and
+// the first N physical rows that no valid slot references.
+__global__ __launch_bounds__(1024) void k_prepare(RunView R)
+{
+    const int64_t rows = R.K + R.N;
+    for (int64_t r = threadIdx.x; r < rows; r += 1024) R.used[r] = 0;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < R.K; j += 1024)
+        if (R.valid[j]) R.used[R.slot_row[j]] = 1;
+    __syncthreads();
+    int carry = 0;
+    for (int64_t base = 0; base < R.K; base += 1024) {
+        const int64_t j = base + threadIdx.x;
+        const int v = (j < R.K && R.valid[j]) ? 1 : 0;
+        int tot;
+        const int off = block_scan_1024(v, &tot);
+        if (v) R.vs[carry + off] = (int32_t)j;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *R.nvalid = carry;
+    int placed = 0;
+    for (int64_t base = 0; base < rows && placed < R.N; base += 1024) {
+        const int64_t r = base + threadIdx.x;
+        const int v = (r < rows && !R.used[r]) ? 1 : 0;
+        int tot;
+        const int off = block_scan_1024(v, &tot);
+        if (v && placed + off < R.N) R.off_row[placed + off] = (int32_t)r;
+        placed += tot;
+    }
+}
+
+// --------------------------------------------------------------- helpers
+__device__ __forceinline__ double sbx_beta(double mc, double eta)
+{
+    const double e = 1.0 / (eta + 1.0);
+    if (mc < 0.5) return pow(2.0 * mc, e);
+    return pow(2.0 - 2.0 * mc, -e);
+}
+
+__device__ __forceinline__ double pm_delta(double x, double lb, double ub, double mm, double xi)
+{
+    const double span = ub - lb;
+    const double e = 1.0 / (xi + 1.0);
+    if (mm < 0.5) {
+        const double d1 = (x - lb) / span;
+        const double base = 2.0 * mm + (1.0 - 2.0 * mm) * pow(1.0 - d1, xi + 1.0);
+        return span * (pow(base, e) - 1.0);
+    }
+    if (mm > 0.5) {
+        const double d2 = (ub - x) / span;
+        const double base = 2.0 * (1.0 - mm) + 2.0 * (mm - 0.5) * pow(1.0 - d2, xi + 1.0);
+        return span * (1.0 - pow(base, e));
+    }
+    return 0.0;
+}
+
+// Sum over the S lanes of a segment (S a power of two <= 64).
+template <int S>
+__device__ __forceinline__ double seg_sum(double v)
+{
+#pragma unroll
+    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, S);
+    return v;
+}
+
+// ------------------------------------------------------------------- init
+// Slot i < N: genes from counter (q, i, 0, TAG_INIT), gene 4q+k from word k,
+// x = lb + (ub-lb) u24 rounded to float; evaluated in the same pass.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_init(RunView R)
+{
+    const int seg = threadIdx.x / S, lane = threadIdx.x % S;
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / S) + seg;
+    if (i >= R.N) return;  // uniform per segment
+    const int Q = (R.d + 3) / 4;
+    float *row = R.X + i * (int64_t)R.ld;
+    const double span = R.ub - R.lb;
+    double gsum = 0.0;
+    float pv[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int q = lane; q < Q; q += S) {
+        const W4 w = draw(R, (uint32_t)q, (uint32_t)i, 0u, TAG_INIT);
+        float x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double scaled = span * unif24(w.w[k]);
+            x[k] = (float)(R.lb + scaled);
+            const int g = 4 * q + k;
+            if (g < R.d && g >= R.m - 1) gsum += (double)dist_term(R.problem, x[k]);
+        }
+        if (q < 2) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pv[k] = x[k];
+        }
+        *reinterpret_cast<float4 *>(row + 4 * q) = make_float4(x[0], x[1], x[2], x[3]);
+    }
+    gsum = seg_sum<S>(gsum);
+    float pos[kMaxM];
+#pragma unroll
+    for (int k = 0; k < kMaxM - 1; ++k) pos[k] = __shfl(pv[k & 3], k >> 2, S);
+    if (lane == 0) {
+        float f[kMaxM];
+        finish_objectives(R.problem, R.m, R.d, pos, gsum, f);
+        for (int k = 0; k < R.m; ++k) R.Fm[i * R.m + k] = f[k];
+        R.valid[i] = 1;
+        R.slot_row[i] = (int32_t)i;
+    }
+}
+
+// empty slots N..K-1 and the generation counter
+__global__ void k_init_empty(RunView R)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + R.N;
+    if (j < R.K) {
+        R.valid[j] = 0;
+        R.slot_row[j] = (int32_t)j;
+        for (int k = 0; k < R.m; ++k) R.Fm[j * R.m + k] = __int_as_float(0x7fc00000);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *R.t_done = 0;
+}
+
+// --------------------------------------------------------------- offspring
+// Mutation sites of child o: events e = 0,1,... with counter (e, o, t,
+// TAG_MUT); U = 1 - u53(w0,w1) in (0,1], gap = floor(log U / log(1-p)),
+// site_e = site_{e-1} + 1 + gap while it stays below d; M_mut = u53(w2,w3).
+// Both children of a pair are drawn at once, S/2 lanes each per round.
+template <int S>
+__device__ void draw_sites(const RunView &R, uint32_t t, int64_t o1, int64_t o2, bool has2,
+                           double lq, int lane, int32_t *s1, double *m1, int32_t *s2, double *m2,
+                           int *n1, int *n2)
+{
+    constexpr int H2 = S / 2;
+    const int c = lane / H2, hl = lane % H2;
+    const int64_t o = c ? o2 : o1;
+    int32_t *sites = c ? s2 : s1;
+    double *mags = c ? m2 : m1;
+    int cur = -1;           // position before this round
+    bool done = c ? !has2 : false;
+    int count = 0;
+    for (int round = 0;; ++round) {
+        const bool any_left = __any(!done);  // wave-uniform continuation
+        if (!any_left) break;
+        const uint32_t e = (uint32_t)(round * H2 + hl);
+        int step = 0;
+        double mag = 0.0;
+        if (!done) {
+            const W4 w = draw(R, e, (uint32_t)o, t, TAG_MUT);
+            const double U = 1.0 - unif53(w.w[0], w.w[1]);
+            double q = log(U) / lq;
+            if (!(q >= 0.0)) q = 0.0;
+            const double gap = floor(q);
+            step = gap >= (double)R.d ? R.d + 1 : 1 + (int)gap;
+            mag = unif53(w.w[2], w.w[3]);
+        }
+        int incl = step;
+#pragma unroll
+        for (int off = 1; off < H2; off <<= 1) {
+            const int y = __shfl_up(incl, off, H2);
+            if (hl >= off) incl += y;
+        }
+        const int pos = cur + incl;
+        if (!done && pos < R.d) {
+            const int idx = round * H2 + hl;
+            if (idx < kMaxSites) {
+                sites[idx] = pos;
+                mags[idx] = mag;
+            } else {
+                atomicAdd(&R.counters[2], 1ull);
+            }
+        }
+        const int last = __shfl(pos, H2 - 1, H2);
+        int mine = (!done && pos < R.d) ? 1 : 0;
+#pragma unroll
+        for (int off = H2 / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, H2);
+        if (!done) {
+            count += mine;
+            cur = last;
+            if (last >= R.d) done = true;
+        }
+    }
+    const int cnt1 = __shfl(count, 0, S);
+    const int cnt2 = __shfl(count, H2, S);
+    *n1 = cnt1 < kMaxSites ? cnt1 : kMaxSites;
+    *n2 = cnt2 < kMaxSites ? cnt2 : kMaxSites;
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
+{
+    constexpr int SEGS = kBlock / S;
+    __shared__ int32_t sh_sites[SEGS][2][kMaxSites];
+    __shared__ double sh_mags[SEGS][2][kMaxSites];
+
+    const int seg = threadIdx.x / S, lane = threadIdx.x % S;
+    const int64_t P = (R.N + 1) / 2;
+    const int64_t p = (int64_t)blockIdx.x * SEGS + seg;
+    const bool active = p < P;
+    const uint32_t t = (uint32_t)(*R.t_done + 1);
+    const int64_t o1 = p, o2 = p + P;
+    const bool has2 = o2 < R.N;
+    const uint32_t nv = (uint32_t)*R.nvalid;
+    if (nv == 0) {  // no parent left (every row was non-finite): offspring are empty
+        if (active && lane == 0) {
+            for (int k = 0; k < R.m; ++k) {
+                R.Fm[(R.K + o1) * R.m + k] = __int_as_float(0x7fc00000);
+                if (has2) R.Fm[(R.K + o2) * R.m + k] = __int_as_float(0x7fc00000);
+            }
+        }
+        return;  // uniform over the grid
+    }
+
+    // random mating: two uniform draws over the valid slots
+    int32_t a = 0, b = 0;
+    if (active) {
+        const W4 w = draw(R, 0u, (uint32_t)p, t, TAG_MATE);
+        a = R.vs[below(w.w[0], nv)];
+        b = R.vs[below(w.w[1], nv)];
+        if (lane == 0) {
+            R.parents[2 * p] = a;
+            R.parents[2 * p + 1] = b;
+        }
+    }
+
+    // mutation sites of both children
+    int n1 = 0, n2 = 0;
+    const double pr = R.p_m / (double)R.d;
+    if (pr > 0.0) {
+        const double lq = log1p(-(pr > 1.0 ? 1.0 : pr));
+        if (active)
+            draw_sites<S>(R, t, o1, o2, has2, lq, lane, sh_sites[seg][0], sh_mags[seg][0],
+                          sh_sites[seg][1], sh_mags[seg][1], &n1, &n2);
+    }
+    __syncthreads();
+    if (!active) return;
+
+    bool nocross = false;
+    if (R.p_c < 1.0) {
+        const W4 w = draw(R, 0u, (uint32_t)p, t, TAG_SBXPAIR);
+        nocross = ((double)w.w[0] * 0x1p-32) > R.p_c;
+    }
+
+    const float *x1row = R.X + (int64_t)R.slot_row[a] * R.ld;
+    const float *x2row = R.X + (int64_t)R.slot_row[b] * R.ld;
+    float *c1row = R.X + (int64_t)R.off_row[o1] * R.ld;
+    float *c2row = has2 ? R.X + (int64_t)R.off_row[o2] * R.ld : nullptr;
+    const int Q = (R.d + 3) / 4;
+    const double lb = R.lb, ub = R.ub;
+    double g1 = 0.0, g2 = 0.0;
+    float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
+
+    for (int q = lane; q < Q; q += S) {
+        const float4 xa = *reinterpret_cast<const float4 *>(x1row + 4 * q);
+        const float4 xb = *reinterpret_cast<const float4 *>(x2row + 4 * q);
+        const float pa[4] = {xa.x, xa.y, xa.z, xa.w};
+        const float pb[4] = {xb.x, xb.y, xb.z, xb.w};
+        const W4 w = draw(R, (uint32_t)q, (uint32_t)p, t, TAG_SBX);
+        double c1[4], c2[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t word = w.w[k];
+            const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
+            double B = sgn * sbx_beta(unif24(word), R.eta_c);
+            if (((word >> 6) & 1u) || nocross) B = 1.0;
+            const double xa_ = (double)pa[k], xb_ = (double)pb[k];
+            const double up = 1.0 + B, dn = 1.0 - B;
+            c1[k] = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
+            c2[k] = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
+        }
+        // polynomial mutation at this quad's sites
+        const int g0 = 4 * q;
+        for (int s = 0; s < n1; ++s) {
+            const int pos = sh_sites[seg][0][s];
+            if (pos >= g0 && pos < g0 + 4) {
+                const int k = pos - g0;
+                const double x = c1[k];
+                c1[k] = dclip(x + pm_delta(x, lb, ub, sh_mags[seg][0][s], R.eta_m), lb, ub);
+            }
+        }
+        for (int s = 0; s < n2; ++s) {
+            const int pos = sh_sites[seg][1][s];
+            if (pos >= g0 && pos < g0 + 4) {
+                const int k = pos - g0;
+                const double x = c2[k];
+                c2[k] = dclip(x + pm_delta(x, lb, ub, sh_mags[seg][1][s], R.eta_m), lb, ub);
+            }
+        }
+        float y1[4], y2[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            y1[k] = (float)c1[k];
+            y2[k] = (float)c2[k];
+            const int g = g0 + k;
+            if (g < R.d && g >= R.m - 1) {
+                g1 += (double)dist_term(R.problem, y1[k]);
+                g2 += (double)dist_term(R.problem, y2[k]);
+            }
+        }
+        if (q < 2) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                pv1[k] = y1[k];
+                pv2[k] = y2[k];
+            }
+        }
+        *reinterpret_cast<float4 *>(c1row + g0) = make_float4(y1[0], y1[1], y1[2], y1[3]);
+        if (has2) *reinterpret_cast<float4 *>(c2row + g0) = make_float4(y2[0], y2[1], y2[2], y2[3]);
+    }
+    g1 = seg_sum<S>(g1);
+    g2 = seg_sum<S>(g2);
+    float pos1[kMaxM], pos2[kMaxM];
+#pragma unroll
+    for (int k = 0; k < kMaxM - 1; ++k) {
+        pos1[k] = __shfl(pv1[k & 3], k >> 2, S);
+        pos2[k] = __shfl(pv2[k & 3], k >> 2, S);
+    }
+    if (lane == 0) {
+        float f[kMaxM];
+        finish_objectives(R.problem, R.m, R.d, pos1, g1, f);
+        float *F1 = R.Fm + (R.K + o1) * R.m;
+        for (int k = 0; k < R.m; ++k) F1[k] = f[k];
+        if (has2) {
+            finish_objectives(R.problem, R.m, R.d, pos2, g2, f);
+            float *F2 = R.Fm + (R.K + o2) * R.m;
+            for (int k = 0; k < R.m; ++k) F2[k] = f[k];
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+int pick_segment(int d)
+{
+    const int Q = (d + 3) / 4;
+    int S = 4;
+    while (S < 64 && S < Q) S <<= 1;
+    return S;
+}
+
+#define RVEA_SEG_DISPATCH(S, KERNEL, GRID_UNITS, STREAM, VIEW)                                 \
+    do {                                                                                     \
+        const int64_t units_ = (GRID_UNITS);                                                 \
+        switch (S) {                                                                         \
+        case 4: KERNEL<4><<<dim3((unsigned)((units_ + 63) / 64)), kBlock, 0, STREAM>>>(VIEW);  \
+            break;                                                                           \
+        case 8: KERNEL<8><<<dim3((unsigned)((units_ + 31) / 32)), kBlock, 0, STREAM>>>(VIEW);  \
+            break;                                                                           \
+        case 16: KERNEL<16><<<dim3((unsigned)((units_ + 15) / 16)), kBlock, 0, STREAM>>>(VIEW); \
+            break;                                                                           \
+        case 32: KERNEL<32><<<dim3((unsigned)((units_ + 7) / 8)), kBlock, 0, STREAM>>>(VIEW);   \
+            break;                                                                           \
+        default: KERNEL<64><<<dim3((unsigned)((units_ + 3) / 4)), kBlock, 0, STREAM>>>(VIEW);   \
+            break;                                                                           \
+        }                                                                                    \
+    } while (0)
+
+hipError_t launch_init(const RunView &R, hipStream_t s)
+{
+    const int S = pick_segment(R.d);
+    if (R.N > 0) RVEA_SEG_DISPATCH(S, k_init, R.N, s, R);
+    const int64_t empty = R.K - R.N;
+    const unsigned g = (unsigned)((empty > 0 ? empty : 1) + 255) / 256;
+    k_init_empty<<<g, 256, 0, s>>>(R);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const RunView &R, hipStream_t s)
+{
+    k_prepare<<<1, 1024, 0, s>>>(R);
+    return hipGetLastError();
+}
+
+hipError_t launch_offspring(const RunView &R, hipStream_t s)
+{
+    const int S = pick_segment(R.d);
+    const int64_t P = (R.N + 1) / 2;
+    RVEA_SEG_DISPATCH(S, k_offspring, P, s, R);
+    return hipGetLastError();
+}
+
+}  // namespace rvea

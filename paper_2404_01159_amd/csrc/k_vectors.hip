@@ -1,0 +1,187 @@
+// k_vectors.hip -- reference-vector kernels.
+//   k_lattice   V_0 (Alg. 2 input): row j of the Das-Dennis simplex lattice
+//               with H divisions, found by unranking the j-th (m-1)-subset
+//               of {1..H+m-1} in lexicographic order (parts a_i = c_i -
+//               c_{i-1} - 1, w = a/H), normalised to unit length
+//   k_gamma     Eq. 5: gamma_j = min over i != j of the angle between v_i and
+//               v_j, double precision, v_i.v_j / (|v_i| |v_j|) as an fma
+//               chain; exactly parallel vectors are skipped, pi/2 if none
+//   k_adapt_v   Alg. 2 line 8 (rule of the cited RVEA): V_j = V0_j o r /
+//               |V0_j o r| with r the survivors' per-objective range; left
+//               unchanged if some range is not positive and finite
+//   k_vec_aux   float copy of V (padded rows) and row norms
+#include "rvea_dev.h"
+#include "rvea_internal.h"
+
+namespace rvea {
+
+__device__ __forceinline__ uint64_t binom(int64_t n, int k)
+{
+    if (k < 0 || n < k) return 0;
+    uint64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+    return r;
+}
+
+__device__ __forceinline__ void write_aux(const RunView &R, int64_t j, const double *v)
+{
+    const int stride = R.m <= 4 ? 4 : 8;
+    double n2 = v[0] * v[0];
+    for (int k = 1; k < R.m; ++k) n2 = fma(v[k], v[k], n2);
+    R.vn[j] = sqrt(n2);
+    for (int k = 0; k < stride; ++k) R.V32[j * stride + k] = k < R.m ? (float)v[k] : 0.0f;
+}
+
+__global__ void k_lattice(RunView R, int H)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= R.K) return;
+    const int m = R.m, kk = m - 1;
+    const int64_t n = (int64_t)H + m - 1;
+    int64_t x = j;
+    int64_t prev = 0;
+    double w[kMaxM];
+    for (int i = 0; i < kk; ++i) {
+        int64_t v = prev + 1;
+        for (;; ++v) {
+            const uint64_t cnt = binom(n - v, kk - 1 - i);
+            if ((uint64_t)x < cnt) break;
+            x -= (int64_t)cnt;
+        }
+        w[i] = (double)(v - prev - 1) / (double)H;
+        prev = v;
+    }
+    w[m - 1] = (double)((int64_t)H + m - prev - 1) / (double)H;
+    double n2 = w[0] * w[0];
+    for (int k = 1; k < m; ++k) n2 = fma(w[k], w[k], n2);
+    const double nrm = sqrt(n2);
+    double v[kMaxM];
+    for (int k = 0; k < m; ++k) {
+        v[k] = w[k] / nrm;
+        R.V0[j * m + k] = v[k];
+        R.V[j * m + k] = v[k];
+    }
+    write_aux(R, j, v);
+}
+
+__global__ void k_vec_aux(RunView R)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= R.K) return;
+    double v[kMaxM];
+    for (int k = 0; k < R.m; ++k) v[k] = R.V[j * R.m + k];
+    write_aux(R, j, v);
+}
+
+template <int MD>
+__global__ __launch_bounds__(256) void k_gamma(RunView R, int force)
+{
+    if (!force && *R.vchanged == 0) return;
+    __shared__ double sv[256 * MD];
+    __shared__ double sn[256];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double vj[MD];
+    double nj = 1.0;
+    if (j < R.K) {
+#pragma unroll
+        for (int k = 0; k < MD; ++k) vj[k] = R.V[j * MD + k];
+        nj = R.vn[j];
+    } else {
+#pragma unroll
+        for (int k = 0; k < MD; ++k) vj[k] = 0.0;
+    }
+    double best = -2.0;
+    bool found = false;
+    for (int64_t base = 0; base < R.K; base += 256) {
+        __syncthreads();
+        const int64_t ii = base + threadIdx.x;
+        if (ii < R.K) {
+#pragma unroll
+            for (int k = 0; k < MD; ++k) sv[threadIdx.x * MD + k] = R.V[ii * MD + k];
+            sn[threadIdx.x] = R.vn[ii];
+        }
+        __syncthreads();
+        const int cnt = (int)(R.K - base < 256 ? R.K - base : 256);
+        for (int q = 0; q < cnt; ++q) {
+            const int64_t i = base + q;
+            const double *vi = sv + q * MD;
+            double s = vi[0] * vj[0];
+#pragma unroll
+            for (int k = 1; k < MD; ++k) s = fma(vi[k], vj[k], s);
+            const double c = s / (sn[q] * nj);
+            if (i != j && c < 1.0 && (!found || c > best)) {
+                best = c;
+                found = true;
+            }
+        }
+    }
+    if (j < R.K) R.gamma[j] = found ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
+}
+
+__global__ void k_adapt_v(RunView R)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r[kMaxM];
+    bool ok = true;
+    for (int k = 0; k < R.m; ++k) {
+        const uint32_t lo = R.rbits[k], hi = R.rbits[R.m + k];
+        if (lo == 0xffffffffu) {
+            ok = false;
+            break;
+        }
+        r[k] = (double)ord_dec(hi) - (double)ord_dec(lo);
+        ok = ok && r[k] > 0.0 && isfinite(r[k]);
+    }
+    if (j == 0) *R.vchanged = ok ? 1 : 0;
+    if (!ok || j >= R.K) return;
+    double w[kMaxM];
+    for (int k = 0; k < R.m; ++k) w[k] = R.V0[j * R.m + k] * r[k];
+    double n2 = w[0] * w[0];
+    for (int k = 1; k < R.m; ++k) n2 = fma(w[k], w[k], n2);
+    const double nrm = sqrt(n2);
+    double v[kMaxM];
+    for (int k = 0; k < R.m; ++k) {
+        v[k] = w[k] / nrm;
+        R.V[j * R.m + k] = v[k];
+    }
+    write_aux(R, j, v);
+}
+
+// ------------------------------------------------------------- launchers
+static unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_gamma(const RunView &R, hipStream_t s, int force)
+{
+    switch (R.m) {
+    case 2: k_gamma<2><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
+    case 3: k_gamma<3><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
+    case 4: k_gamma<4><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
+    case 5: k_gamma<5><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
+    case 6: k_gamma<6><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
+    case 7: k_gamma<7><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
+    default: k_gamma<8><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice(const RunView &R, hipStream_t s, int H)
+{
+    k_lattice<<<blocks(R.K, 256), 256, 0, s>>>(R, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_vec_aux(const RunView &R, hipStream_t s)
+{
+    k_vec_aux<<<blocks(R.K, 256), 256, 0, s>>>(R);
+    return hipGetLastError();
+}
+
+hipError_t launch_adapt(const RunView &R, hipStream_t s)
+{
+    k_adapt_v<<<blocks(R.K, 256), 256, 0, s>>>(R);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gamma(R, s, 0);
+}
+
+}  // namespace rvea

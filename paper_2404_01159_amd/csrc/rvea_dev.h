@@ -1,0 +1,132 @@
+// rvea_dev.h -- device-side definitions shared by the library's kernels.
+//
+// Contents: the run view handed to every kernel, Philox4x32-10 (Salmon,
+// Moraes, Dror, Shaw, SC'11) in its counter-based form, the uniform
+// variates built from its words, and order-preserving float encodings used
+// by the atomic min/max reductions.  gfx950 only; compiled with
+// -ffp-contract=off, so every fused multiply-add below is written as fma().
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rvea {
+
+// Philox stream tags (fourth counter word).  The other three counter words
+// are (sub-index, individual or pair, generation); the key is the run seed.
+enum : uint32_t { TAG_INIT = 0, TAG_MATE = 1, TAG_SBX = 2, TAG_SBXPAIR = 3, TAG_MUT = 4 };
+
+constexpr int kMaxM = 8;         // objectives supported
+constexpr int kTile = 32;        // reference vectors per association tile
+constexpr int kMaxSites = 32;    // mutation sites held per child
+constexpr int kBlock = 256;      // threads per block for the streaming kernels
+
+// Everything a kernel needs to find the run's buffers.  Passed by value.
+struct RunView {
+    int m, d, ld, problem;
+    int64_t N, K, M;  // parent slots K, offspring N, merged rows M = K + N
+    uint32_t key0, key1;
+    int t_max, period;
+    double alpha, eta_c, eta_m, p_c, p_m, lb, ub;
+    int KC, CS;  // association: number of vector chunks and chunk length
+
+    float *X;           // (K+N) x ld physical gene rows
+    int32_t *slot_row;  // K: physical row of each slot
+    int32_t *off_row;   // N: physical row of each offspring this generation
+    uint8_t *valid;     // K
+    float *Fm;          // M x m merged objectives (slots, then offspring)
+    float *Fn;          // K x m next-generation objectives
+    int32_t *row_n;     // K next slot rows
+    uint8_t *valid_n;   // K
+    uint8_t *mvalid;    // M: row takes part in the selection
+    int32_t *parents;   // ceil(N/2) x 2 slot indices
+    int32_t *vs;        // K valid slots, ascending
+    int32_t *nvalid;    // 1
+    int32_t *used;      // K+N physical-row flags
+    double *V0, *V;     // K x m
+    float *V32;         // K x 4 or K x 8 (padded with zeros)
+    double *vn;         // K norms of V
+    double *gamma;      // K
+    uint32_t *zbits;    // m ordered-encoded ideal point
+    uint32_t *rbits;    // 2m ordered-encoded survivor min / max
+    float *pmax;        // KC x M chunk maxima
+    uint32_t *pmask;    // KC x M candidate-tile masks
+    int32_t *assoc;     // M
+    double *apd;        // M
+    unsigned long long *key;  // K
+    int32_t *surv;      // K
+    int64_t *t_done;    // completed generations
+    unsigned long long *counters;  // 0 non-finite rows, 1 full rescans, 2 site overflow
+    int32_t *vchanged;  // 1: adaptation changed V
+};
+
+// ---------------------------------------------------------------- Philox
+struct W4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ W4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t x0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        const uint32_t x2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = x0;
+        c2 = x2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    W4 r;
+    r.w[0] = c0;
+    r.w[1] = c1;
+    r.w[2] = c2;
+    r.w[3] = c3;
+    return r;
+}
+
+__device__ __forceinline__ W4 draw(const RunView &R, uint32_t sub, uint32_t idx, uint32_t gen,
+                                   uint32_t tag)
+{
+    return philox4x32_10(sub, idx, gen, tag, R.key0, R.key1);
+}
+
+// top 24 bits as a uniform in [0,1)
+__device__ __forceinline__ double unif24(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
+
+// 53-bit uniform in [0,1) from two words
+__device__ __forceinline__ double unif53(uint32_t a, uint32_t b)
+{
+    const uint64_t v = ((uint64_t)(a >> 5) << 26) | (uint64_t)(b >> 6);
+    return (double)v * 0x1p-53;
+}
+
+// integer uniform in [0,n) by multiply-shift
+__device__ __forceinline__ uint32_t below(uint32_t w, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+// ------------------------------------------------- ordered float encodings
+__device__ __forceinline__ uint32_t ord_enc(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord_dec(uint32_t e)
+{
+    const uint32_t u = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ double dclip(double x, double lo, double hi)
+{
+    x = x < lo ? lo : x;
+    return x > hi ? hi : x;
+}
+
+}  // namespace rvea

@@ -1,0 +1,601 @@
+// rvea_host.hip -- the C ABI of include/rvea.h: argument checks, workspace
+// layout inside the caller's device buffer, launch sequencing, state access
+// and per-kernel event timing.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "rvea.h"
+#include "rvea_dev.h"
+#include "rvea_internal.h"
+
+using namespace rvea;
+
+namespace {
+
+constexpr int kKernels = 4;  // timed kernel ids: offspring, assoc, rerank, gamma
+
+struct Layout {
+    int ld, stride, KC, CS;
+    size_t off[40];
+    size_t total;
+};
+
+enum Buf {
+    B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_FN, B_ROWN, B_VALIDN, B_MVALID, B_PARENTS, B_VS,
+    B_NVALID, B_USED, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
+    B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_COUNT
+};
+
+int64_t binomial(int64_t n, int64_t k)
+{
+    if (k < 0 || n < 0 || k > n) return 0;
+    if (k > n - k) k = n - k;
+    int64_t r = 1;
+    for (int64_t i = 1; i <= k; ++i) {
+        r = r * (n - k + i) / i;
+        if (r > ((int64_t)1 << 40)) return -1;
+    }
+    return r;
+}
+
+int find_H(int m, int64_t K)
+{
+    for (int h = 1; h < (1 << 24); ++h) {
+        const int64_t c = binomial((int64_t)h + m - 1, m - 1);
+        if (c == K) return h;
+        if (c < 0 || c > K) return 0;
+    }
+    return 0;
+}
+
+rvea_status check_args(int problem, int m, int d, int64_t N, int64_t K, const rvea_params &p)
+{
+    if (problem < 1 || problem > 3) return RVEA_EINVAL;
+    if (m < 2 || m > kMaxM || d < m || d > (1 << 26)) return RVEA_EINVAL;
+    if (K < 1 || K > (int64_t)1 << 27 || N < 1 || N > K) return RVEA_EINVAL;
+    if (find_H(m, K) == 0) return RVEA_EINVAL;
+    if (!(p.alpha >= 0) || !(p.fr > 0) || p.t_max < 1 || p.reserved != 0) return RVEA_EINVAL;
+    if (!(p.eta_c >= 0) || !(p.eta_m >= 0) || !(p.p_c >= 0 && p.p_c <= 1)) return RVEA_EINVAL;
+    if (!(p.p_m >= 0 && p.p_m <= 4)) return RVEA_EINVAL;
+    if (!(p.lb < p.ub) || !std::isfinite(p.lb) || !std::isfinite(p.ub)) return RVEA_EINVAL;
+    return RVEA_OK;
+}
+
+void make_layout(int m, int d, int64_t N, int64_t K, Layout &L)
+{
+    const int64_t M = K + N;
+    L.ld = (d + 31) / 32 * 32;
+    L.stride = m <= 4 ? 4 : 8;
+    // association grid: enough (row block x vector chunk) workgroups to fill
+    // the 256 CUs several times over, chunks of at most 32 tiles
+    const int64_t nbi = (M + assoc_rows_per_block() - 1) / assoc_rows_per_block();
+    int64_t kc0 = (2048 + nbi - 1) / nbi;
+    if (kc0 < 1) kc0 = 1;
+    int64_t cs = (K + kc0 - 1) / kc0;
+    cs = (cs + kTile - 1) / kTile * kTile;
+    cs = std::min<int64_t>(std::max<int64_t>(cs, kTile), 32 * kTile);
+    L.CS = (int)cs;
+    L.KC = (int)((K + cs - 1) / cs);
+    const int64_t P = (N + 1) / 2;
+    const size_t sz[B_COUNT] = {
+        (size_t)(K + N) * L.ld * 4, (size_t)K * 4, (size_t)N * 4, (size_t)K,
+        (size_t)M * m * 4, (size_t)K * m * 4, (size_t)K * 4, (size_t)K, (size_t)M,
+        (size_t)P * 2 * 4, (size_t)K * 4, 4, (size_t)(K + N) * 4, (size_t)K * m * 8,
+        (size_t)K * m * 8, (size_t)K * L.stride * 4, (size_t)K * 8, (size_t)K * 8,
+        (size_t)m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
+        (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4};
+    size_t o = 0;
+    for (int b = 0; b < B_COUNT; ++b) {
+        L.off[b] = o;
+        o += (sz[b] + 255) / 256 * 256;
+    }
+    L.total = o;
+}
+
+}  // namespace
+
+struct rvea_run_s {
+    RunView R;
+    Layout L;
+    hipStream_t stream;
+    int device;
+    int H;
+    int64_t t;  // completed generations (host mirror)
+    int phase;  // 0 ready, 1 stepped, 2 selected
+    bool has_selection;
+    rvea_params params;
+    char err[512];
+    int timing;  // kernel mask
+    struct Ev {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> events;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+rvea_status fail(rvea_run r, hipError_t e, const char *what)
+{
+    if (r) std::snprintf(r->err, sizeof r->err, "%s: %s", what, hipGetErrorString(e));
+    return RVEA_EDEVICE;
+}
+
+#define HIPCHK(r, call)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return fail(r, e_, #call);                                     \
+    } while (0)
+
+hipEvent_t take_event(rvea_run r)
+{
+    if (!r->pool.empty()) {
+        hipEvent_t e = r->pool.back();
+        r->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// launches fn; when timing is on, brackets it with events on the run's stream
+template <class Fn>
+rvea_status timed(rvea_run r, int id, Fn fn, const char *what)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool on = (r->timing >> id) & 1;
+    if (on) {
+        a = take_event(r);
+        b = take_event(r);
+        if (a && b) HIPCHK(r, hipEventRecord(a, r->stream));
+    }
+    hipError_t e = fn();
+    if (e != hipSuccess) return fail(r, e, what);
+    if (on && a && b) {
+        HIPCHK(r, hipEventRecord(b, r->stream));
+        r->events.push_back({id, a, b});
+    }
+    return RVEA_OK;
+}
+
+rvea_status check_counters(rvea_run r)
+{
+    unsigned long long c[3];
+    HIPCHK(r, hipMemcpy(c, r->R.counters, sizeof c, hipMemcpyDeviceToHost));
+    if (c[2] != 0) {
+        std::snprintf(r->err, sizeof r->err,
+                      "a child drew more than %d mutation sites; lower p_m", kMaxSites);
+        return RVEA_EUNSUPPORTED;
+    }
+    return RVEA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rvea_status rvea_default_params(rvea_params *out)
+{
+    if (!out) return RVEA_EINVAL;
+    out->alpha = 2.0;
+    out->fr = 0.1;
+    out->t_max = 100;
+    out->reserved = 0;
+    out->eta_c = 20.0;
+    out->eta_m = 20.0;
+    out->p_c = 1.0;
+    out->p_m = 1.0;
+    out->lb = 0.0;
+    out->ub = 1.0;
+    return RVEA_OK;
+}
+
+rvea_status rvea_lattice_divisions(int m, int64_t K, int *H)
+{
+    if (!H || m < 1 || K < 1) return RVEA_EINVAL;
+    const int h = find_H(m, K);
+    if (h == 0) return RVEA_EINVAL;
+    *H = h;
+    return RVEA_OK;
+}
+
+rvea_status rvea_footprint(int problem, int m, int d, int64_t N, int64_t K,
+                           const rvea_params *params, size_t *bytes)
+{
+    rvea_params p;
+    if (params) p = *params; else rvea_default_params(&p);
+    if (!bytes) return RVEA_EINVAL;
+    const rvea_status st = check_args(problem, m, d, N, K, p);
+    if (st != RVEA_OK) return st;
+    Layout L;
+    make_layout(m, d, N, K, L);
+    *bytes = L.total;
+    return RVEA_OK;
+}
+
+rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
+                        const rvea_params *params, void *workspace, size_t workspace_bytes,
+                        void *hip_stream, rvea_run *out)
+{
+    if (!out) return RVEA_EINVAL;
+    *out = nullptr;
+    rvea_params p;
+    if (params) p = *params; else rvea_default_params(&p);
+    rvea_status st = check_args(problem, m, d, N, K, p);
+    if (st != RVEA_OK) return st;
+    if (!workspace || ((uintptr_t)workspace & 255u)) return RVEA_EINVAL;
+    Layout L;
+    make_layout(m, d, N, K, L);
+    if (workspace_bytes < L.total) return RVEA_ENOMEM;
+
+    rvea_run r = new rvea_run_s();
+    r->L = L;
+    r->stream = (hipStream_t)hip_stream;
+    r->H = find_H(m, K);
+    r->t = 0;
+    r->phase = 0;
+    r->has_selection = false;
+    r->params = p;
+    r->err[0] = 0;
+    r->timing = 0;
+    if (hipGetDevice(&r->device) != hipSuccess) r->device = 0;
+
+    RunView &R = r->R;
+    std::memset(&R, 0, sizeof R);
+    R.m = m;
+    R.d = d;
+    R.ld = L.ld;
+    R.problem = problem;
+    R.N = N;
+    R.K = K;
+    R.M = K + N;
+    R.key0 = (uint32_t)seed;
+    R.key1 = (uint32_t)(seed >> 32);
+    R.t_max = p.t_max;
+    {
+        const double x = p.fr * (double)p.t_max;
+        double c = std::ceil(x - 1e-9 * (x > 1.0 ? x : 1.0));
+        R.period = c < 1.0 ? 1 : (int)c;
+    }
+    R.alpha = p.alpha;
+    R.eta_c = p.eta_c;
+    R.eta_m = p.eta_m;
+    R.p_c = p.p_c;
+    R.p_m = p.p_m;
+    R.lb = p.lb;
+    R.ub = p.ub;
+    R.KC = L.KC;
+    R.CS = L.CS;
+    char *w = (char *)workspace;
+    R.X = (float *)(w + L.off[B_X]);
+    R.slot_row = (int32_t *)(w + L.off[B_SLOT]);
+    R.off_row = (int32_t *)(w + L.off[B_OFF]);
+    R.valid = (uint8_t *)(w + L.off[B_VALID]);
+    R.Fm = (float *)(w + L.off[B_FM]);
+    R.Fn = (float *)(w + L.off[B_FN]);
+    R.row_n = (int32_t *)(w + L.off[B_ROWN]);
+    R.valid_n = (uint8_t *)(w + L.off[B_VALIDN]);
+    R.mvalid = (uint8_t *)(w + L.off[B_MVALID]);
+    R.parents = (int32_t *)(w + L.off[B_PARENTS]);
+    R.vs = (int32_t *)(w + L.off[B_VS]);
+    R.nvalid = (int32_t *)(w + L.off[B_NVALID]);
+    R.used = (int32_t *)(w + L.off[B_USED]);
+    R.V0 = (double *)(w + L.off[B_V0]);
+    R.V = (double *)(w + L.off[B_V]);
+    R.V32 = (float *)(w + L.off[B_V32]);
+    R.vn = (double *)(w + L.off[B_VN]);
+    R.gamma = (double *)(w + L.off[B_GAMMA]);
+    R.zbits = (uint32_t *)(w + L.off[B_ZBITS]);
+    R.rbits = (uint32_t *)(w + L.off[B_RBITS]);
+    R.pmax = (float *)(w + L.off[B_PMAX]);
+    R.pmask = (uint32_t *)(w + L.off[B_PMASK]);
+    R.assoc = (int32_t *)(w + L.off[B_ASSOC]);
+    R.apd = (double *)(w + L.off[B_APD]);
+    R.key = (unsigned long long *)(w + L.off[B_KEY]);
+    R.surv = (int32_t *)(w + L.off[B_SURV]);
+    R.t_done = (int64_t *)(w + L.off[B_TDONE]);
+    R.counters = (unsigned long long *)(w + L.off[B_COUNTERS]);
+    R.vchanged = (int32_t *)(w + L.off[B_VCHANGED]);
+
+    hipError_t e = hipMemsetAsync(R.counters, 0, 3 * sizeof(unsigned long long), r->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(R.vchanged, 0, 4, r->stream);
+    if (e == hipSuccess) e = launch_lattice(R, r->stream, r->H);
+    if (e == hipSuccess) e = launch_gamma(R, r->stream, 1);
+    if (e == hipSuccess) e = launch_init(R, r->stream);
+    if (e != hipSuccess) {
+        fail(r, e, "initialization");
+        delete r;
+        return RVEA_EDEVICE;
+    }
+    *out = r;
+    return RVEA_OK;
+}
+
+rvea_status rvea_step(rvea_run r)
+{
+    if (!r) return RVEA_EINVAL;
+    if (r->phase != 0) return RVEA_ESTATE;
+    HIPCHK(r, launch_prepare(r->R, r->stream));
+    rvea_status st = timed(r, 0, [&] { return launch_offspring(r->R, r->stream); }, "offspring");
+    if (st != RVEA_OK) return st;
+    r->phase = 1;
+    return RVEA_OK;
+}
+
+rvea_status rvea_select(rvea_run r)
+{
+    if (!r) return RVEA_EINVAL;
+    if (r->phase != 1) return RVEA_ESTATE;
+    HIPCHK(r, launch_select_front(r->R, r->stream));
+    rvea_status st = timed(r, 1, [&] { return launch_assoc(r->R, r->stream); }, "assoc");
+    if (st != RVEA_OK) return st;
+    st = timed(r, 2, [&] { return launch_rerank(r->R, r->stream); }, "rerank");
+    if (st != RVEA_OK) return st;
+    HIPCHK(r, launch_select_back(r->R, r->stream));
+    r->t += 1;
+    r->phase = 2;
+    r->has_selection = true;
+    return RVEA_OK;
+}
+
+rvea_status rvea_adapt(rvea_run r)
+{
+    if (!r) return RVEA_EINVAL;
+    if (r->phase != 2) return RVEA_ESTATE;
+    if (r->t % r->R.period == 0) {
+        rvea_status st = timed(r, 3, [&] { return launch_adapt(r->R, r->stream); }, "adapt");
+        if (st != RVEA_OK) return st;
+    }
+    r->phase = 0;
+    return RVEA_OK;
+}
+
+rvea_status rvea_run_generations(rvea_run r, int n)
+{
+    if (!r || n < 0) return RVEA_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        rvea_status st = rvea_step(r);
+        if (st == RVEA_OK) st = rvea_select(r);
+        if (st == RVEA_OK) st = rvea_adapt(r);
+        if (st != RVEA_OK) return st;
+    }
+    return RVEA_OK;
+}
+
+rvea_status rvea_synchronize(rvea_run r)
+{
+    if (!r) return RVEA_EINVAL;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    return check_counters(r);
+}
+
+namespace {
+
+// copy the gene rows rows[0..n) of the pool into dst (n x d, host)
+rvea_status copy_rows(rvea_run r, const std::vector<int32_t> &rows, float *dst)
+{
+    const RunView &R = r->R;
+    const size_t rowb = (size_t)R.d * 4;
+    const size_t pool_bytes = (size_t)(R.K + R.N) * R.ld * 4;
+    if (pool_bytes <= ((size_t)1 << 28) || rows.size() * 4 > (size_t)(R.K + R.N)) {
+        std::vector<float> pool((size_t)(R.K + R.N) * R.ld);
+        HIPCHK(r, hipMemcpy(pool.data(), R.X, pool_bytes, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < rows.size(); ++i)
+            std::memcpy(dst + i * R.d, pool.data() + (size_t)rows[i] * R.ld, rowb);
+    } else {
+        for (size_t i = 0; i < rows.size(); ++i)
+            HIPCHK(r, hipMemcpy(dst + i * R.d, R.X + (size_t)rows[i] * R.ld, rowb,
+                                hipMemcpyDeviceToHost));
+    }
+    return RVEA_OK;
+}
+
+}  // namespace
+
+rvea_status rvea_get_state(rvea_run r, float *X, float *F, uint8_t *valid, double *V,
+                           double *V0, double *gamma, int64_t *t)
+{
+    if (!r) return RVEA_EINVAL;
+    const RunView &R = r->R;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    std::vector<uint8_t> vh(R.K);
+    HIPCHK(r, hipMemcpy(vh.data(), R.valid, R.K, hipMemcpyDeviceToHost));
+    if (valid) std::memcpy(valid, vh.data(), R.K);
+    if (X) {
+        std::vector<int32_t> rows(R.K);
+        HIPCHK(r, hipMemcpy(rows.data(), R.slot_row, R.K * 4, hipMemcpyDeviceToHost));
+        rvea_status st = copy_rows(r, rows, X);
+        if (st != RVEA_OK) return st;
+        for (int64_t j = 0; j < R.K; ++j)
+            if (!vh[j]) std::memset(X + j * R.d, 0, (size_t)R.d * 4);
+    }
+    if (F) HIPCHK(r, hipMemcpy(F, R.Fm, (size_t)R.K * R.m * 4, hipMemcpyDeviceToHost));
+    if (V) HIPCHK(r, hipMemcpy(V, R.V, (size_t)R.K * R.m * 8, hipMemcpyDeviceToHost));
+    if (V0) HIPCHK(r, hipMemcpy(V0, R.V0, (size_t)R.K * R.m * 8, hipMemcpyDeviceToHost));
+    if (gamma) HIPCHK(r, hipMemcpy(gamma, R.gamma, (size_t)R.K * 8, hipMemcpyDeviceToHost));
+    if (t) HIPCHK(r, hipMemcpy(t, R.t_done, 8, hipMemcpyDeviceToHost));
+    return check_counters(r);
+}
+
+rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uint8_t *valid,
+                           const double *V, const double *gamma, int64_t t)
+{
+    if (!r || !X || !F || !valid || t < 0) return RVEA_EINVAL;
+    if (r->phase != 0) return RVEA_ESTATE;
+    const RunView &R = r->R;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipMemcpy2D(R.X, (size_t)R.ld * 4, X, (size_t)R.d * 4, (size_t)R.d * 4,
+                          (size_t)R.K, hipMemcpyHostToDevice));
+    std::vector<int32_t> rows(R.K);
+    std::vector<uint8_t> vv(R.K);
+    for (int64_t j = 0; j < R.K; ++j) {
+        rows[j] = (int32_t)j;
+        vv[j] = valid[j] ? 1 : 0;
+    }
+    HIPCHK(r, hipMemcpy(R.slot_row, rows.data(), R.K * 4, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(R.valid, vv.data(), R.K, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(R.Fm, F, (size_t)R.K * R.m * 4, hipMemcpyHostToDevice));
+    if (V) {
+        HIPCHK(r, hipMemcpy(R.V, V, (size_t)R.K * R.m * 8, hipMemcpyHostToDevice));
+        HIPCHK(r, launch_vec_aux(R, r->stream));
+    }
+    if (gamma)
+        HIPCHK(r, hipMemcpy(R.gamma, gamma, (size_t)R.K * 8, hipMemcpyHostToDevice));
+    else if (V)
+        HIPCHK(r, launch_gamma(R, r->stream, 1));
+    HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    r->t = t;
+    r->has_selection = false;
+    return RVEA_OK;
+}
+
+rvea_status rvea_get_offspring(rvea_run r, float *X, float *F, int32_t *parents)
+{
+    if (!r) return RVEA_EINVAL;
+    if (r->phase == 0) return RVEA_ESTATE;
+    const RunView &R = r->R;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    if (X) {
+        std::vector<int32_t> rows(R.N);
+        HIPCHK(r, hipMemcpy(rows.data(), R.off_row, R.N * 4, hipMemcpyDeviceToHost));
+        rvea_status st = copy_rows(r, rows, X);
+        if (st != RVEA_OK) return st;
+    }
+    if (F)
+        HIPCHK(r, hipMemcpy(F, R.Fm + R.K * R.m, (size_t)R.N * R.m * 4,
+                            hipMemcpyDeviceToHost));
+    if (parents)
+        HIPCHK(r, hipMemcpy(parents, R.parents, (size_t)((R.N + 1) / 2) * 8,
+                            hipMemcpyDeviceToHost));
+    return check_counters(r);
+}
+
+rvea_status rvea_get_selection(rvea_run r, float *zstar, int32_t *assoc, double *apd,
+                               int32_t *surv)
+{
+    if (!r) return RVEA_EINVAL;
+    if (!r->has_selection || r->phase == 1) return RVEA_ESTATE;
+    const RunView &R = r->R;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    if (zstar) {
+        uint32_t zb[kMaxM];
+        HIPCHK(r, hipMemcpy(zb, R.zbits, R.m * 4, hipMemcpyDeviceToHost));
+        for (int k = 0; k < R.m; ++k) {
+            const uint32_t e = zb[k];
+            const uint32_t u = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
+            std::memcpy(zstar + k, &u, 4);
+        }
+    }
+    if (assoc) HIPCHK(r, hipMemcpy(assoc, R.assoc, R.M * 4, hipMemcpyDeviceToHost));
+    if (apd) HIPCHK(r, hipMemcpy(apd, R.apd, R.M * 8, hipMemcpyDeviceToHost));
+    if (surv) HIPCHK(r, hipMemcpy(surv, R.surv, R.K * 4, hipMemcpyDeviceToHost));
+    return RVEA_OK;
+}
+
+rvea_status rvea_get_rows(rvea_run r, int offspring, const int64_t *idx, int64_t n, float *X,
+                          float *F)
+{
+    if (!r || (n > 0 && !idx) || n < 0) return RVEA_EINVAL;
+    if (offspring && r->phase == 0) return RVEA_ESTATE;
+    const RunView &R = r->R;
+    const int64_t lim = offspring ? R.N : R.K;
+    for (int64_t q = 0; q < n; ++q)
+        if (idx[q] < 0 || idx[q] >= lim) return RVEA_EINVAL;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    std::vector<int32_t> map(lim);
+    HIPCHK(r, hipMemcpy(map.data(), offspring ? R.off_row : R.slot_row, lim * 4,
+                        hipMemcpyDeviceToHost));
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t i = idx[q];
+        if (X)
+            HIPCHK(r, hipMemcpy(X + q * R.d, R.X + (size_t)map[i] * R.ld, (size_t)R.d * 4,
+                                hipMemcpyDeviceToHost));
+        if (F)
+            HIPCHK(r, hipMemcpy(F + q * R.m, R.Fm + ((offspring ? R.K : 0) + i) * R.m,
+                                (size_t)R.m * 4, hipMemcpyDeviceToHost));
+    }
+    return check_counters(r);
+}
+
+rvea_status rvea_get_counters(rvea_run r, rvea_counters *out)
+{
+    if (!r || !out) return RVEA_EINVAL;
+    unsigned long long c[3];
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipMemcpy(c, r->R.counters, sizeof c, hipMemcpyDeviceToHost));
+    out->nonfinite_rows = (int64_t)c[0];
+    out->full_rescans = (int64_t)c[1];
+    out->generations = r->t;
+    return RVEA_OK;
+}
+
+rvea_status rvea_set_timing(rvea_run r, int kernel_mask)
+{
+    if (!r) return RVEA_EINVAL;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    for (auto &ev : r->events) {
+        r->pool.push_back(ev.a);
+        r->pool.push_back(ev.b);
+    }
+    r->events.clear();
+    r->timing = kernel_mask & ((1 << kKernels) - 1);
+    return RVEA_OK;
+}
+
+rvea_status rvea_kernel_time(rvea_run r, int kernel, double *ms, int64_t *launches)
+{
+    if (!r || kernel < 0 || kernel >= kKernels || !ms || !launches) return RVEA_EINVAL;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto &ev : r->events) {
+        if (ev.id != kernel) continue;
+        float x = 0.f;
+        HIPCHK(r, hipEventElapsedTime(&x, ev.a, ev.b));
+        tot += x;
+        ++n;
+    }
+    *ms = tot;
+    *launches = n;
+    return RVEA_OK;
+}
+
+rvea_status rvea_destroy(rvea_run r)
+{
+    if (!r) return RVEA_EINVAL;
+    (void)hipStreamSynchronize(r->stream);
+    for (auto &ev : r->events) {
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+    }
+    for (auto e : r->pool) (void)hipEventDestroy(e);
+    delete r;
+    return RVEA_OK;
+}
+
+const char *rvea_status_str(rvea_status s)
+{
+    switch (s) {
+    case RVEA_OK: return "ok";
+    case RVEA_EINVAL: return "invalid argument";
+    case RVEA_ENOMEM: return "workspace too small";
+    case RVEA_EDEVICE: return "HIP device error";
+    case RVEA_ESTATE: return "call out of order";
+    case RVEA_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char *rvea_last_error(rvea_run r) { return r ? r->err : "no run"; }
+
+}  // extern "C"

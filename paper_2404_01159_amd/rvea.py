@@ -1,0 +1,249 @@
+"""Python binding of librvea.so (include/rvea.h).
+
+Argument marshalling only: every step of a generation runs in the library's
+HIP kernels.  PyTorch supplies the device workspace (a uint8 tensor whose
+data pointer is handed to rvea_create) and the HIP stream.  There is no
+fallback: if the library is missing or fails to load, importing this module
+raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librvea.so")
+
+RVEA_OK, RVEA_EINVAL, RVEA_ENOMEM, RVEA_EDEVICE, RVEA_ESTATE, RVEA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+LINEAR_MULTIMODAL, SPHERE_UNIMODAL, SPHERE_MULTIMODAL = 1, 2, 3
+KERNEL_OFFSPRING, KERNEL_ASSOC, KERNEL_RERANK, KERNEL_GAMMA = 0, 1, 2, 3
+
+EXPORTS = [
+    "rvea_default_params", "rvea_lattice_divisions", "rvea_footprint", "rvea_create",
+    "rvea_step", "rvea_select", "rvea_adapt", "rvea_run_generations", "rvea_get_state",
+    "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
+    "rvea_get_counters",
+    "rvea_set_timing", "rvea_kernel_time", "rvea_synchronize", "rvea_destroy",
+    "rvea_status_str", "rvea_last_error",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("alpha", C.c_double), ("fr", C.c_double), ("t_max", C.c_int32),
+        ("reserved", C.c_int32), ("eta_c", C.c_double), ("eta_m", C.c_double),
+        ("p_c", C.c_double), ("p_m", C.c_double), ("lb", C.c_double), ("ub", C.c_double),
+    ]
+
+
+class Counters(C.Structure):
+    _fields_ = [("nonfinite_rows", C.c_int64), ("full_rescans", C.c_int64),
+                ("generations", C.c_int64)]
+
+
+class RveaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, u64, sz = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_size_t
+    sig = {
+        "rvea_default_params": [P],
+        "rvea_lattice_divisions": [i32, i64, P],
+        "rvea_footprint": [i32, i32, i32, i64, i64, P, P],
+        "rvea_create": [i32, i32, i32, i64, i64, u64, P, P, sz, P, P],
+        "rvea_step": [P], "rvea_select": [P], "rvea_adapt": [P],
+        "rvea_run_generations": [P, i32],
+        "rvea_get_state": [P, P, P, P, P, P, P, P],
+        "rvea_set_state": [P, P, P, P, P, P, i64],
+        "rvea_get_offspring": [P, P, P, P],
+        "rvea_get_selection": [P, P, P, P, P],
+        "rvea_get_rows": [P, i32, P, i64, P, P],
+        "rvea_get_counters": [P, P],
+        "rvea_set_timing": [P, i32],
+        "rvea_kernel_time": [P, i32, P, P],
+        "rvea_synchronize": [P], "rvea_destroy": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.rvea_status_str.argtypes = [C.c_int]
+    L.rvea_status_str.restype = C.c_char_p
+    L.rvea_last_error.argtypes = [P]
+    L.rvea_last_error.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def default_params(**kw):
+    p = Params()
+    lib.rvea_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def lattice_divisions(m, K):
+    h = C.c_int(0)
+    st = lib.rvea_lattice_divisions(m, K, C.byref(h))
+    return h.value if st == RVEA_OK else None
+
+
+def footprint(problem, m, d, N, K, params=None):
+    b = C.c_size_t(0)
+    st = lib.rvea_footprint(problem, m, d, N, K, C.byref(params) if params else None,
+                            C.byref(b))
+    if st != RVEA_OK:
+        raise RveaError(st, lib.rvea_status_str(st).decode())
+    return b.value
+
+
+class Run:
+    """One RVEA run resident on a HIP device.
+
+    ``workspace`` may be a preallocated torch uint8 CUDA tensor of at least
+    ``footprint`` bytes; otherwise one is allocated on ``device``.
+    """
+
+    def __init__(self, problem, m, d, N, K, seed=0, params=None, device="cuda:0",
+                 stream=None, workspace=None):
+        import torch
+
+        self.problem, self.m, self.d, self.N, self.K = problem, m, d, N, K
+        self.M = K + N
+        self.seed = seed
+        self.params = params if params is not None else default_params()
+        self.bytes = footprint(problem, m, d, N, K, self.params)
+        dev = torch.device(device)
+        if workspace is None:
+            workspace = torch.empty(self.bytes + 256, dtype=torch.uint8, device=dev)
+        self._ws = workspace
+        base = workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        avail = workspace.numel() - (aligned - base)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._h = C.c_void_p(0)
+        with torch.cuda.device(dev):
+            st = lib.rvea_create(problem, m, d, N, K, C.c_uint64(seed), C.byref(self.params),
+                                 C.c_void_p(aligned), avail, C.c_void_p(self.stream.cuda_stream),
+                                 C.byref(self._h))
+        if st != RVEA_OK:
+            raise RveaError(st, "rvea_create: " + lib.rvea_status_str(st).decode())
+
+    # ------------------------------------------------------------------
+    def _chk(self, st, what):
+        if st != RVEA_OK:
+            msg = lib.rvea_last_error(self._h).decode() if self._h else ""
+            raise RveaError(st, f"{what}: {lib.rvea_status_str(st).decode()} {msg}")
+
+    def step(self):
+        self._chk(lib.rvea_step(self._h), "rvea_step")
+
+    def select(self):
+        self._chk(lib.rvea_select(self._h), "rvea_select")
+
+    def adapt(self):
+        self._chk(lib.rvea_adapt(self._h), "rvea_adapt")
+
+    def generation(self):
+        self.step()
+        self.select()
+        self.adapt()
+
+    def run(self, n):
+        self._chk(lib.rvea_run_generations(self._h, n), "rvea_run_generations")
+
+    def synchronize(self):
+        self._chk(lib.rvea_synchronize(self._h), "rvea_synchronize")
+
+    def get_state(self, genes=True):
+        K, d, m = self.K, self.d, self.m
+        X = np.zeros((K, d), np.float32) if genes else None
+        F = np.zeros((K, m), np.float32)
+        valid = np.zeros(K, np.uint8)
+        V = np.zeros((K, m), np.float64)
+        V0 = np.zeros((K, m), np.float64)
+        g = np.zeros(K, np.float64)
+        t = C.c_int64(0)
+        self._chk(lib.rvea_get_state(self._h, _p(X), _p(F), _p(valid), _p(V), _p(V0), _p(g),
+                                     C.byref(t)), "rvea_get_state")
+        return dict(X=X, F=F, valid=valid, V=V, V0=V0, gamma=g, t=t.value)
+
+    def set_state(self, X, F, valid, V=None, gamma=None, t=0):
+        X = np.ascontiguousarray(X, np.float32)
+        F = np.ascontiguousarray(F, np.float32)
+        valid = np.ascontiguousarray(valid, np.uint8)
+        assert X.shape == (self.K, self.d) and F.shape == (self.K, self.m)
+        V = None if V is None else np.ascontiguousarray(V, np.float64)
+        gamma = None if gamma is None else np.ascontiguousarray(gamma, np.float64)
+        self._chk(lib.rvea_set_state(self._h, _p(X), _p(F), _p(valid), _p(V), _p(gamma),
+                                     int(t)), "rvea_set_state")
+
+    def get_offspring(self, genes=True):
+        N, d, m = self.N, self.d, self.m
+        X = np.zeros((N, d), np.float32) if genes else None
+        F = np.zeros((N, m), np.float32)
+        parents = np.zeros(((N + 1) // 2, 2), np.int32)
+        self._chk(lib.rvea_get_offspring(self._h, _p(X), _p(F), _p(parents)),
+                  "rvea_get_offspring")
+        return dict(X=X, F=F, parents=parents)
+
+    def get_selection(self):
+        z = np.zeros(self.m, np.float32)
+        assoc = np.zeros(self.M, np.int32)
+        apd = np.zeros(self.M, np.float64)
+        surv = np.zeros(self.K, np.int32)
+        self._chk(lib.rvea_get_selection(self._h, _p(z), _p(assoc), _p(apd), _p(surv)),
+                  "rvea_get_selection")
+        return dict(zstar=z, assoc=assoc, apd=apd, surv=surv)
+
+    def get_rows(self, idx, offspring=False, genes=True):
+        idx = np.ascontiguousarray(idx, np.int64)
+        X = np.zeros((len(idx), self.d), np.float32) if genes else None
+        F = np.zeros((len(idx), self.m), np.float32)
+        self._chk(lib.rvea_get_rows(self._h, 1 if offspring else 0, _p(idx), len(idx), _p(X),
+                                    _p(F)), "rvea_get_rows")
+        return X, F
+
+    def counters(self):
+        c = Counters()
+        self._chk(lib.rvea_get_counters(self._h, C.byref(c)), "rvea_get_counters")
+        return dict(nonfinite_rows=c.nonfinite_rows, full_rescans=c.full_rescans,
+                    generations=c.generations)
+
+    def set_timing(self, kernels):
+        """kernels: iterable of kernel ids to bracket with events (empty = off)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << int(k)
+        self._chk(lib.rvea_set_timing(self._h, mask), "rvea_set_timing")
+
+    def kernel_time(self, kernel):
+        ms = C.c_double(0)
+        n = C.c_int64(0)
+        self._chk(lib.rvea_kernel_time(self._h, kernel, C.byref(ms), C.byref(n)),
+                  "rvea_kernel_time")
+        return ms.value, n.value
+
+    def close(self):
+        if self._h:
+            lib.rvea_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
