@@ -95,11 +95,9 @@ def main():
     warm.close()
     del warm
 
+    # timed pass: a fresh run, every generation one HIP-graph launch
     run = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"],
                 params=prm, device="cuda:0")
-    names = ["offspring", "assoc", "rerank", "adapt"]
-    if not a.no_timing:
-        run.set_timing([0, 1, 2])
     run.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -108,7 +106,19 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     gens_per_s = a.steps / el
+    st = run.get_state(genes=False)
+    counters = run.counters()
+    run.close()
 
+    # kernel pass: the same run again with HIP events around the kernels
+    # (launched one by one, since a replayed graph cannot carry fresh events)
+    names = ["offspring", "assoc", "rerank", "adapt"]
+    if not a.no_timing:
+        run = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"],
+                    params=prm, device="cuda:0")
+        run.set_timing([0, 1, 2])
+        run.run(a.steps)
+        run.synchronize()
     roof = None
     per_kernel = {}
     if not a.no_timing:
@@ -129,8 +139,7 @@ def main():
             roof = dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                         frac=ach / PEAK_FP32_TFLOPS, traffic=None, kernel=dom,
                         avg_launch_us=avg_ms * 1e3, launches=n)
-    st = run.get_state(genes=False)
-    run.close()
+        run.close()
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -154,6 +163,7 @@ def main():
                    "generations_timed": a.steps, "survivors_final": int(st["valid"].sum())},
         "roofline": roof,
         "kernels_avg_us": {k: v[0] * 1e3 for k, v in per_kernel.items()},
+        "counters": counters,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

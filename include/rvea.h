@@ -119,8 +119,15 @@ rvea_status rvea_select(rvea_run run);
  * and recomputes gamma; otherwise does nothing. */
 rvea_status rvea_adapt(rvea_run run);
 
-/* n x (rvea_step, rvea_select, rvea_adapt). */
+/* n x (rvea_step, rvea_select, rvea_adapt).  Unless disabled with
+ * rvea_set_graphs or while kernel timing is on, each generation is one
+ * launch of a HIP graph captured once per run (a second graph holds the
+ * adapting generation).  Results are identical either way. */
 rvea_status rvea_run_generations(rvea_run run, int n);
+
+/* 1 (default) = rvea_run_generations replays captured HIP graphs, 0 = it
+ * launches every kernel individually. */
+rvea_status rvea_set_graphs(rvea_run run, int enable);
 
 /* Copies the run state to host memory (waits for the stream).  Any pointer
  * may be NULL.  Layouts, row-major: X K x d float, F K x m float,

@@ -50,46 +50,145 @@ __device__ int block_scan_1024(int v, int *total)
     return before + x - v;
 }
 
-// One block of 1024 threads: list the valid slots in ascending order and
-// the first N physical rows that no valid slot references.
-__global__ __launch_bounds__(1024) void k_prepare(RunView R)
+// Per generation, before the offspring: (1) every row a valid slot points
+// at is stamped with the generation number and each block of 256 slots
+// counts its valid slots; (2) each block adds the counts of the blocks
+// before it and writes its valid slots to their ascending positions, and
+// reserves room for its unstamped (free) rows with one atomic add.  The
+// order of the free rows does not matter: it only decides where each child's
+// genes are stored.
+__device__ __forceinline__ int block_scan_256(int v, int *total)
 {
-    const int64_t rows = R.K + R.N;
-    for (int64_t r = threadIdx.x; r < rows; r += 1024) R.used[r] = 0;
-    __syncthreads();
-    for (int64_t j = threadIdx.x; j < R.K; j += 1024)
-        if (R.valid[j]) R.used[R.slot_row[j]] = 1;
-    __syncthreads();
-    int carry = 0;
-    for (int64_t base = 0; base < R.K; base += 1024) {
-        const int64_t j = base + threadIdx.x;
-        const int v = (j < R.K && R.valid[j]) ? 1 : 0;
-        int tot;
-        const int off = block_scan_1024(v, &tot);
-        if (v) R.vs[carry + off] = (int32_t)j;
-        carry += tot;
+    __shared__ int wsum[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    if (threadIdx.x == 0) *R.nvalid = carry;
-    int placed = 0;
-    for (int64_t base = 0; base < rows && placed < R.N; base += 1024) {
-        const int64_t r = base + threadIdx.x;
-        const int v = (r < rows && !R.used[r]) ? 1 : 0;
-        int tot;
-        const int off = block_scan_1024(v, &tot);
-        if (v && placed + off < R.N) R.off_row[placed + off] = (int32_t)r;
-        placed += tot;
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        before += w < wid ? wsum[w] : 0;
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_prep_count(RunView R)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int32_t gen = (int32_t)(*R.t_done + 1);
+    int v = 0;
+    if (j < R.K && R.valid[j]) {
+        v = 1;
+        R.stamp[R.slot_row[j]] = gen;
+    }
+    const unsigned long long b = __ballot(v);
+    __shared__ int wc[4];
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        R.bcount[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+        if (blockIdx.x == 0) *R.freecnt = 0;
     }
 }
 
+__global__ __launch_bounds__(256) void k_prep_write(RunView R)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int32_t gen = (int32_t)(*R.t_done + 1);
+    // offset of this block's valid slots
+    int pre = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) pre += R.bcount[b];
+    int dummy;
+    const int zero = block_scan_256(pre, &dummy);
+    (void)zero;
+    const int offset = dummy;  // total of the per-thread partial sums
+    const int v = (j < R.K && R.valid[j]) ? 1 : 0;
+    int tot;
+    const int pos = block_scan_256(v, &tot);
+    if (v) R.vs[offset + pos] = (int32_t)j;
+    const int64_t nblk = (R.K + 255) / 256;
+    if ((int64_t)blockIdx.x == nblk - 1 && threadIdx.x == 0) *R.nvalid = offset + tot;
+    // free rows of this block
+    const int fr = (j < R.K + R.N && R.stamp[j] != gen) ? 1 : 0;
+    int ftot;
+    const int fpos = block_scan_256(fr, &ftot);
+    __shared__ int fbase;
+    if (threadIdx.x == 0) fbase = ftot ? atomicAdd(R.freecnt, ftot) : 0;
+    __syncthreads();
+    if (fr && fbase + fpos < R.N) R.off_row[fbase + fpos] = (int32_t)j;
+}
+
 // --------------------------------------------------------------- helpers
-__device__ __forceinline__ double sbx_beta(double mc, double eta)
+// z^n for a positive integer n (square and multiply, n uniform); the
+// default distribution index eta = 20 (n = 21) gets straight-line code
+__device__ __forceinline__ double ipow(double z, int n)
+{
+    if (n == 21) {
+        const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4, z16 = z8 * z8;
+        return (z16 * z4) * z;
+    }
+    double r = 1.0, b = z;
+    while (n) {
+        if (n & 1) r *= b;
+        n >>= 1;
+        if (n) b *= b;
+    }
+    return r;
+}
+
+// 1/z for z in (0, 4): hardware estimate plus two Newton-Raphson steps,
+// within one binary64 ulp
+__device__ __forceinline__ double recip(double z)
+{
+    double r = __builtin_amdgcn_rcp(z);
+    r = fma(r, fma(-z, r, 1.0), r);
+    r = fma(r, fma(-z, r, 1.0), r);
+    return r;
+}
+
+__device__ __attribute__((noinline)) double sbx_beta_pow(double mc, double eta)
 {
     const double e = 1.0 / (eta + 1.0);
     if (mc < 0.5) return pow(2.0 * mc, e);
     return pow(2.0 - 2.0 * mc, -e);
 }
 
-__device__ __forceinline__ double pm_delta(double x, double lb, double ub, double mm, double xi)
+// SBX spread factor (Appendix B): (2 M_c)^(1/(eta+1)) below 1/2,
+// (2 - 2 M_c)^(-1/(eta+1)) above, in binary64.  When eta+1 is a small
+// integer n the root a^(-1/n) starts from a single-precision estimate and
+// takes two Newton steps on z^-n = a (z <- z (1 + (1 - a z^n)/n), division
+// free, error ~ (n+1)/2 e^2 per step), which leaves it within a few binary64
+// ulps; other eta use pow().
+__device__ __forceinline__ double sbx_beta(double mc, double eta, int n)
+{
+    if (n > 0) {
+        if (mc == 0.0) return 0.0;
+        const double a = mc < 0.5 ? 2.0 * mc : 2.0 - 2.0 * mc;
+        const float ninv = 1.0f / (float)n;
+        double z = (double)exp2f(-log2f((float)a) * ninv);
+        const double dn = 1.0 / (double)n;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const double e = fma(-a, ipow(z, n), 1.0);
+            z = fma(z * e, dn, z);
+        }
+        return mc < 0.5 ? recip(z) : z;
+    }
+    return sbx_beta_pow(mc, eta);
+}
+
+// rare (about one site per child): kept out of line so it does not raise the
+// register budget of the gene loop
+__device__ __attribute__((noinline)) double pm_delta(double x, double lb, double ub, double mm,
+                                                    double xi)
 {
     const double span = ub - lb;
     const double e = 1.0 / (xi + 1.0);
@@ -296,6 +395,8 @@ __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
     float *c2row = has2 ? R.X + (int64_t)R.off_row[o2] * R.ld : nullptr;
     const int Q = (R.d + 3) / 4;
     const double lb = R.lb, ub = R.ub;
+    const double np1 = R.eta_c + 1.0;
+    const int nroot = (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
     double g1 = 0.0, g2 = 0.0;
     float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
 
@@ -305,42 +406,28 @@ __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
         const float pa[4] = {xa.x, xa.y, xa.z, xa.w};
         const float pb[4] = {xb.x, xb.y, xb.z, xb.w};
         const W4 w = draw(R, (uint32_t)q, (uint32_t)p, t, TAG_SBX);
-        double c1[4], c2[4];
+        const int g0 = 4 * q;
+        float y1[4], y2[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t word = w.w[k];
             const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
-            double B = sgn * sbx_beta(unif24(word), R.eta_c);
+            double B = sgn * sbx_beta(unif24(word), R.eta_c, nroot);
             if (((word >> 6) & 1u) || nocross) B = 1.0;
             const double xa_ = (double)pa[k], xb_ = (double)pb[k];
             const double up = 1.0 + B, dn = 1.0 - B;
-            c1[k] = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
-            c2[k] = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
-        }
-        // polynomial mutation at this quad's sites
-        const int g0 = 4 * q;
-        for (int s = 0; s < n1; ++s) {
-            const int pos = sh_sites[seg][0][s];
-            if (pos >= g0 && pos < g0 + 4) {
-                const int k = pos - g0;
-                const double x = c1[k];
-                c1[k] = dclip(x + pm_delta(x, lb, ub, sh_mags[seg][0][s], R.eta_m), lb, ub);
-            }
-        }
-        for (int s = 0; s < n2; ++s) {
-            const int pos = sh_sites[seg][1][s];
-            if (pos >= g0 && pos < g0 + 4) {
-                const int k = pos - g0;
-                const double x = c2[k];
-                c2[k] = dclip(x + pm_delta(x, lb, ub, sh_mags[seg][1][s], R.eta_m), lb, ub);
-            }
-        }
-        float y1[4], y2[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            y1[k] = (float)c1[k];
-            y2[k] = (float)c2[k];
+            double c1 = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
+            double c2 = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
+            // polynomial mutation if this gene is one of the child's sites
             const int g = g0 + k;
+            for (int s_ = 0; s_ < n1; ++s_)
+                if (sh_sites[seg][0][s_] == g)
+                    c1 = dclip(c1 + pm_delta(c1, lb, ub, sh_mags[seg][0][s_], R.eta_m), lb, ub);
+            for (int s_ = 0; s_ < n2; ++s_)
+                if (sh_sites[seg][1][s_] == g)
+                    c2 = dclip(c2 + pm_delta(c2, lb, ub, sh_mags[seg][1][s_], R.eta_m), lb, ub);
+            y1[k] = (float)c1;
+            y2[k] = (float)c2;
             if (g < R.d && g >= R.m - 1) {
                 g1 += (double)dist_term(R.problem, y1[k]);
                 g2 += (double)dist_term(R.problem, y2[k]);
@@ -415,7 +502,9 @@ hipError_t launch_init(const RunView &R, hipStream_t s)
 
 hipError_t launch_prepare(const RunView &R, hipStream_t s)
 {
-    k_prepare<<<1, 1024, 0, s>>>(R);
+    const unsigned nb = (unsigned)((R.K + R.N + 255) / 256);
+    k_prep_count<<<nb, 256, 0, s>>>(R);
+    k_prep_write<<<nb, 256, 0, s>>>(R);
     return hipGetLastError();
 }
 

@@ -26,6 +26,10 @@ namespace rvea {
 __global__ void k_sel_reset(RunView R)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) {  // Eq. 4 penalty factor m (t/t_max)^alpha of this generation
+        const double tcur = (double)(*R.t_done + 1);
+        *R.pen = (double)R.m * pow(tcur / (double)R.t_max, R.alpha);
+    }
     if (j < R.K) {
         R.key[j] = ~0ull;
         R.surv[j] = 0x7fffffff;
@@ -37,22 +41,39 @@ __global__ void k_sel_reset(RunView R)
     }
 }
 
+// wave-wide minimum / maximum of an ordered encoding
+__device__ __forceinline__ uint32_t wave_min(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
 // rows that take part: valid parent slots and all offspring with finite F
-__global__ void k_ideal(RunView R)
+__global__ __launch_bounds__(256) void k_ideal(RunView R)
 {
     __shared__ uint32_t smin[kMaxM];
     if (threadIdx.x < kMaxM) smin[threadIdx.x] = 0xffffffffu;
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = false;
     if (i < R.M) {
-        bool ok = i >= R.K || R.valid[i];
+        ok = i >= R.K || R.valid[i];
         bool fin = true;
         for (int k = 0; k < R.m; ++k) fin = fin && isfinite(R.Fm[i * R.m + k]);
         if (ok && !fin) atomicAdd(&R.counters[0], 1ull);
         ok = ok && fin;
         R.mvalid[i] = ok ? 1 : 0;
-        if (ok)
-            for (int k = 0; k < R.m; ++k) atomicMin(&smin[k], ord_enc(R.Fm[i * R.m + k]));
+    }
+    for (int k = 0; k < R.m; ++k) {
+        const uint32_t e = wave_min(ok ? ord_enc(R.Fm[i * R.m + k]) : 0xffffffffu);
+        if ((threadIdx.x & 63) == 0 && e != 0xffffffffu) atomicMin(&smin[k], e);
     }
     __syncthreads();
     if (threadIdx.x < R.m && smin[threadIdx.x] != 0xffffffffu)
@@ -78,9 +99,13 @@ __device__ __forceinline__ float dotf(const float *f, const float4 *v)
     return s;
 }
 
-template <int MD, int RR>
-__global__ __launch_bounds__(256) void k_assoc(RunView R)
+// GAMMA = false: rows are the merged objective rows f' = F - z*.
+// GAMMA = true:  rows are the reference vectors themselves (Eq. 5), with the
+// pair (j, j) excluded.
+template <int MD, int RR, bool GAMMA>
+__global__ __launch_bounds__(256) void k_assoc(RunView R, int gate)
 {
+    if (GAMMA && !gate && *R.vchanged == 0) return;  // uniform: vectors unchanged
     constexpr int NV4 = MD <= 4 ? 1 : 2;  // float4 per vector
     __shared__ float4 sv[1024 * NV4];
     const int c = blockIdx.y;
@@ -94,10 +119,11 @@ __global__ __launch_bounds__(256) void k_assoc(RunView R)
         const int v = idx / NV4;
         sv[idx] = v < nvec ? Vg[(j0 + v) * NV4 + (idx % NV4)] : pad;
     }
+    const int64_t nrows = GAMMA ? R.K : R.M;
 
     float z[MD];
 #pragma unroll
-    for (int k = 0; k < MD; ++k) z[k] = ord_dec(R.zbits[k]);
+    for (int k = 0; k < MD; ++k) z[k] = GAMMA ? 0.f : ord_dec(R.zbits[k]);
     float f[RR][MD], e2[RR], cm[RR];
     uint32_t mk[RR];
     int64_t rows[RR];
@@ -105,11 +131,14 @@ __global__ __launch_bounds__(256) void k_assoc(RunView R)
     for (int r = 0; r < RR; ++r) {
         const int64_t i = (int64_t)blockIdx.x * (256 * RR) + r * 256 + threadIdx.x;
         rows[r] = i;
-        const bool ok = i < R.M && R.mvalid[i];
+        const bool ok = i < nrows && (GAMMA || R.mvalid[i]);
         float n2 = 0.f;
 #pragma unroll
         for (int k = 0; k < MD; ++k) {
-            f[r][k] = ok ? R.Fm[i * MD + k] - z[k] : 0.f;
+            if (GAMMA)
+                f[r][k] = ok ? R.V32[i * (NV4 * 4) + k] : 0.f;
+            else
+                f[r][k] = ok ? R.Fm[i * MD + k] - z[k] : 0.f;
             n2 = fmaf(f[r][k], f[r][k], n2);
         }
         e2[r] = two_eps(sqrtf(n2));
@@ -123,6 +152,7 @@ __global__ __launch_bounds__(256) void k_assoc(RunView R)
 #pragma unroll
         for (int r = 0; r < RR; ++r) tm[r] = -INFINITY;
         const float4 *tv = sv + tl * kTile * NV4;
+        const int64_t jt = j0 + (int64_t)tl * kTile;
 #pragma unroll 4
         for (int jj = 0; jj < kTile; jj += 2) {
             float4 va[NV4], vb[NV4];
@@ -133,8 +163,12 @@ __global__ __launch_bounds__(256) void k_assoc(RunView R)
             }
 #pragma unroll
             for (int r = 0; r < RR; ++r) {
-                const float sa = dotf<MD>(f[r], va);
-                const float sb = dotf<MD>(f[r], vb);
+                float sa = dotf<MD>(f[r], va);
+                float sb = dotf<MD>(f[r], vb);
+                if (GAMMA) {
+                    sa = rows[r] == jt + jj ? -INFINITY : sa;
+                    sb = rows[r] == jt + jj + 1 ? -INFINITY : sb;
+                }
                 tm[r] = fmaxf(tm[r], fmaxf(sa, sb));
             }
         }
@@ -153,7 +187,7 @@ __global__ __launch_bounds__(256) void k_assoc(RunView R)
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
         const int64_t i = rows[r];
-        if (i < R.M) {
+        if (i < nrows) {
             R.pmax[(int64_t)c * R.M + i] = cm[r];
             R.pmask[(int64_t)c * R.M + i] = mk[r];
         }
@@ -169,78 +203,251 @@ __device__ __forceinline__ double dotd(const double *a, const double *b)
     return s;
 }
 
-template <int MD>
-__global__ __launch_bounds__(256) void k_rerank(RunView R)
+// Re-rank: one 64-lane wave per 16 rows, in three phases.
+//   1. four lanes per row split the row's vector chunks: maximum of the chunk
+//      maxima (threshold gmax - 2 eps), then the tiles of the chunks above
+//      the threshold become work items (row, first vector of the tile);
+//   2. the wave walks the flattened (item, vector) space, one vector per
+//      lane: binary64 cosine f.v / (|f| |v|) as an fma chain, then the best
+//      value of each item with the lowest index over its 32 lanes;
+//   3. one lane per row: the best of its items, then angle, APD and the
+//      per-vector atomic minimum (selection), or gamma (GAMMA: rows are the
+//      vectors, i != j, exactly parallel vectors skipped).
+// A row with more than kItems candidate tiles, or left without a usable
+// candidate, is scanned in full in phase 3 (counted).
+constexpr int kItems = 8;
+constexpr int kRows = 16;  // rows per wave
+
+template <int MD, bool GAMMA>
+__global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= R.M) return;
-    if (!R.mvalid[i]) {
-        R.assoc[i] = -1;
-        R.apd[i] = INFINITY;
-        return;
-    }
-    const double tcur = (double)(*R.t_done + 1);
-    const double pen = (double)MD * pow(tcur / (double)R.t_max, R.alpha);
-    double f[MD];
-    float f32[MD];
-    float n2f = 0.f;
+    if (GAMMA && !gate && *R.vchanged == 0) return;  // uniform: vectors unchanged
+    __shared__ double s_f[kRows][MD];
+    __shared__ double s_nrm[kRows];
+    __shared__ int s_state[kRows];  // 0 inactive, 1 items, 2 zero row, 3 full scan
+    __shared__ int s_cnt[kRows], s_off[kRows];
+    __shared__ int s_row[kRows * kItems], s_j0[kRows * kItems];
+    __shared__ double s_best[kRows * kItems];
+    __shared__ int s_bj[kRows * kItems], s_dup[kRows * kItems];
+
+    const int t = threadIdx.x;
+    const int r = t >> 2, sub = t & 3;
+    const int64_t base = (int64_t)blockIdx.x * kRows;
+    const int64_t i = base + r;
+    const int64_t nrows = GAMMA ? R.K : R.M;
+
+    // ---- phase 1
+    int state = 0, cnt = 0;
+    float thr = 0.f;
+    const bool act = i < nrows && (GAMMA || R.mvalid[i]);
+    if (act) {
+        double f[MD], nrm;
+        float n2f = 0.f;
 #pragma unroll
-    for (int k = 0; k < MD; ++k) {
-        const float zk = ord_dec(R.zbits[k]);
-        const float Fk = R.Fm[i * MD + k];
-        f[k] = (double)Fk - (double)zk;
-        f32[k] = Fk - zk;
-        n2f = fmaf(f32[k], f32[k], n2f);
-    }
-    double n2 = f[0] * f[0];
+        for (int k = 0; k < MD; ++k) {
+            float fk;
+            if (GAMMA) {
+                f[k] = R.V[i * MD + k];
+                fk = R.V32[i * (MD <= 4 ? 4 : 8) + k];
+            } else {
+                const float zk = ord_dec(R.zbits[k]);
+                const float Fk = R.Fm[i * MD + k];
+                f[k] = (double)Fk - (double)zk;
+                fk = Fk - zk;
+            }
+            n2f = fmaf(fk, fk, n2f);
+        }
+        if (GAMMA) {
+            nrm = R.vn[i];
+        } else {
+            double n2 = f[0] * f[0];
 #pragma unroll
-    for (int k = 1; k < MD; ++k) n2 = fma(f[k], f[k], n2);
-    const double nrm = sqrt(n2);
-    if (nrm == 0.0) {
-        R.assoc[i] = 0;
-        R.apd[i] = 0.0;
-        atomicMin(&R.key[0], 0ull);
-        return;
+            for (int k = 1; k < MD; ++k) n2 = fma(f[k], f[k], n2);
+            nrm = sqrt(n2);
+        }
+        if (sub == 0) {
+#pragma unroll
+            for (int k = 0; k < MD; ++k) s_f[r][k] = f[k];
+            s_nrm[r] = nrm;
+        }
+        state = (!GAMMA && nrm == 0.0) ? 2 : 1;
+        const float e2 = two_eps(sqrtf(n2f));
+        float gm = -INFINITY;
+#pragma unroll 8
+        for (int c = sub; c < R.KC; c += 4) gm = fmaxf(gm, R.pmax[(int64_t)c * R.M + i]);
+        thr = gm - e2;
     }
-    const float e2 = two_eps(sqrtf(n2f));
-    float gmax = -INFINITY;
-    for (int c = 0; c < R.KC; ++c) gmax = fmaxf(gmax, R.pmax[(int64_t)c * R.M + i]);
-    const float thr = gmax - e2;
-    double best = -INFINITY;
-    int64_t bj = -1;
-    for (int c = 0; c < R.KC; ++c) {
-        if (!(R.pmax[(int64_t)c * R.M + i] >= thr)) continue;
-        uint32_t mk = R.pmask[(int64_t)c * R.M + i];
-        while (mk) {
-            const int tl = __ffs(mk) - 1;
-            mk &= mk - 1;
-            const int64_t jlo = (int64_t)c * R.CS + (int64_t)tl * kTile;
-            const int64_t jhi = jlo + kTile < R.K ? jlo + kTile : R.K;
-            for (int64_t j = jlo; j < jhi; ++j) {
-                const double cv = dotd<MD>(f, R.V + j * MD) / (nrm * R.vn[j]);
-                if (cv > best) {
+    // the four lanes of a row are adjacent: combine over xor 1, 2
+    thr = fmaxf(thr, __shfl_xor(thr, 1, 64));
+    thr = fmaxf(thr, __shfl_xor(thr, 2, 64));
+    // candidate tiles of this lane's chunks (at most kItems kept per lane)
+    int mine = 0, mc[kItems];
+    uint32_t mm[kItems];
+    if (act && state == 1) {
+#pragma unroll 4
+        for (int c = sub; c < R.KC; c += 4) {
+            if (R.pmax[(int64_t)c * R.M + i] >= thr) {
+                const uint32_t mk = R.pmask[(int64_t)c * R.M + i];
+                if (mine < kItems) {
+                    mc[mine] = c;
+                    mm[mine] = mk;
+                }
+                ++mine;
+                cnt += __popc(mk);
+            }
+        }
+    }
+    int tot = cnt;
+    tot += __shfl_xor(tot, 1, 64);
+    tot += __shfl_xor(tot, 2, 64);
+    int more = mine > kItems ? 1 : 0;
+    more |= __shfl_xor(more, 1, 64);
+    more |= __shfl_xor(more, 2, 64);
+    if (act && state == 1 && (tot < 1 || tot > kItems || more)) state = 3;
+    // exclusive prefix of the tile counts over the row's four lanes
+    int pre = cnt;
+    {
+        const int a1 = __shfl_up(pre, 1, 64);
+        const int c1 = sub >= 1 ? a1 : 0;
+        const int a2 = __shfl_up(pre, 2, 64);
+        const int a3 = __shfl_up(pre, 3, 64);
+        pre = c1 + (sub >= 2 ? a2 : 0) + (sub >= 3 ? a3 : 0);
+    }
+    if (sub == 0) {
+        s_state[r] = act ? state : 0;
+        s_cnt[r] = (act && state == 1) ? tot : 0;
+    }
+    __syncthreads();
+    if (t < kRows) {  // rows' item offsets
+        const int v = s_cnt[t];
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < kRows; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (t >= o) incl += y;
+        }
+        s_off[t] = incl - v;
+    }
+    __syncthreads();
+    const int total = s_off[kRows - 1] + s_cnt[kRows - 1];
+    if (act && state == 1) {
+        int q = s_off[r] + pre;
+        for (int u = 0; u < mine && u < kItems; ++u) {
+            uint32_t mk = mm[u];
+            while (mk) {
+                const int tl = __ffs(mk) - 1;
+                mk &= mk - 1;
+                s_row[q] = r;
+                s_j0[q] = (int)((int64_t)mc[u] * R.CS + (int64_t)tl * kTile);
+                ++q;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: flattened (item, vector) space, 32 lanes per item
+    const int rounds = (total * kTile + 63) / 64;
+    for (int k = 0; k < rounds; ++k) {
+        const int e = t + 64 * k;
+        const int item = e >> 5;
+        double best = -INFINITY;
+        int64_t bj = R.K;
+        int dup = 0;
+        if (item < total) {
+            const int row = s_row[item];
+            const int64_t j = (int64_t)s_j0[item] + (e & 31);
+            const int64_t irow = base + row;
+            if (j < R.K && (!GAMMA || j != irow)) {
+                double f[MD];
+#pragma unroll
+                for (int kk = 0; kk < MD; ++kk) f[kk] = s_f[row][kk];
+                const double cv = dotd<MD>(f, R.V + j * MD) / (s_nrm[row] * R.vn[j]);
+                if (GAMMA && cv >= 1.0) {
+                    dup = 1;
+                } else {
                     best = cv;
                     bj = j;
                 }
             }
         }
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 32);
+            const int64_t oj = __shfl_xor(bj, o, 32);
+            dup |= __shfl_xor(dup, o, 32);
+            if (ob > best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if ((t & 31) == 0 && item < total) {
+            s_best[item] = best;
+            s_bj[item] = (int)bj;
+            s_dup[item] = dup;
+        }
     }
-    if (bj < 0) {  // no candidate survived (non-finite float pass): scan everything
+    __syncthreads();
+
+    // ---- phase 3: one lane per row
+    if (t >= kRows) return;
+    const int64_t row_i = base + t;
+    const int st = s_state[t];
+    if (st == 0) {
+        if (!GAMMA && row_i < R.M) {
+            R.assoc[row_i] = -1;
+            R.apd[row_i] = INFINITY;
+        }
+        return;
+    }
+    if (!GAMMA && st == 2) {
+        R.assoc[row_i] = 0;
+        R.apd[row_i] = 0.0;
+        atomicMin(&R.key[0], 0ull);
+        return;
+    }
+    double best = GAMMA ? -2.0 : -INFINITY;
+    int64_t bj = R.K;
+    bool full = st == 3;
+    if (!full) {
+        const int o = s_off[t], n = s_cnt[t];
+        for (int q = o; q < o + n; ++q) {
+            if (s_dup[q]) full = true;
+            const double b = s_best[q];
+            const int64_t j = s_bj[q];
+            if (j < R.K && (b > best || (b == best && j < bj))) {
+                best = b;
+                bj = j;
+            }
+        }
+        if (bj >= R.K) full = true;
+    }
+    double f[MD];
+#pragma unroll
+    for (int k = 0; k < MD; ++k) f[k] = s_f[t][k];
+    const double nrm = s_nrm[t];
+    if (full) {  // the plain definition: every vector, in index order
         atomicAdd(&R.counters[1], 1ull);
+        best = GAMMA ? -2.0 : -INFINITY;
+        bj = GAMMA ? -1 : 0;
         for (int64_t j = 0; j < R.K; ++j) {
+            if (GAMMA && j == row_i) continue;
             const double cv = dotd<MD>(f, R.V + j * MD) / (nrm * R.vn[j]);
-            if (cv > best) {
+            if (GAMMA && cv >= 1.0) continue;
+            if (cv > best || (GAMMA && bj < 0)) {
                 best = cv;
                 bj = j;
             }
         }
-        if (bj < 0) bj = 0;
+    }
+    if (GAMMA) {
+        R.gamma[row_i] = bj >= 0 ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
+        return;
     }
     const double cc = best > 1.0 ? 1.0 : (best < -1.0 ? -1.0 : best);
     const double th = acos(cc);
-    const double a = (1.0 + pen * th / R.gamma[bj]) * nrm;
-    R.assoc[i] = (int32_t)bj;
-    R.apd[i] = a;
+    const double a = (1.0 + *R.pen * th / R.gamma[bj]) * nrm;
+    R.assoc[row_i] = (int32_t)bj;
+    R.apd[row_i] = a;
     atomicMin(&R.key[bj], (unsigned long long)__double_as_longlong(a));
 }
 
@@ -273,7 +480,7 @@ __global__ void k_newpop(RunView R)
 
 // commit the new population and count the generation; also reduce the
 // survivors' per-objective extremes for a possible adaptation
-__global__ void k_commit(RunView R)
+__global__ __launch_bounds__(256) void k_commit(RunView R)
 {
     __shared__ uint32_t smin[kMaxM], smax[kMaxM];
     if (threadIdx.x < kMaxM) {
@@ -282,17 +489,24 @@ __global__ void k_commit(RunView R)
     }
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint8_t v = 0;
     if (j < R.K) {
-        const uint8_t v = R.valid_n[j];
+        v = R.valid_n[j];
         R.valid[j] = v;
         R.slot_row[j] = R.row_n[j];
-        for (int k = 0; k < R.m; ++k) {
+    }
+    for (int k = 0; k < R.m; ++k) {
+        uint32_t e = 0xffffffffu;
+        if (j < R.K) {
             const float x = R.Fn[j * R.m + k];
             R.Fm[j * R.m + k] = x;
-            if (v) {
-                atomicMin(&smin[k], ord_enc(x));
-                atomicMax(&smax[k], ord_enc(x));
-            }
+            if (v) e = ord_enc(x);
+        }
+        const uint32_t lo = wave_min(e);
+        const uint32_t hi = wave_max(e == 0xffffffffu ? 0u : e);
+        if ((threadIdx.x & 63) == 0) {
+            if (lo != 0xffffffffu) atomicMin(&smin[k], lo);
+            atomicMax(&smax[k], hi);
         }
     }
     __syncthreads();
@@ -329,7 +543,7 @@ hipError_t launch_assoc(const RunView &R, hipStream_t s)
 {
     constexpr int RR = 4;
     const dim3 grid(blocks(R.M, 256 * RR), (unsigned)R.KC);
-#define RVEA_ASSOC(MV) k_assoc<MV, RR><<<grid, 256, 0, s>>>(R)
+#define RVEA_ASSOC(MV) k_assoc<MV, RR, false><<<grid, 256, 0, s>>>(R, 1)
     RVEA_M_DISPATCH(R.m, RVEA_ASSOC);
 #undef RVEA_ASSOC
     return hipGetLastError();
@@ -337,9 +551,25 @@ hipError_t launch_assoc(const RunView &R, hipStream_t s)
 
 hipError_t launch_rerank(const RunView &R, hipStream_t s)
 {
-#define RVEA_RERANK(MV) k_rerank<MV><<<blocks(R.M, 256), 256, 0, s>>>(R)
+#define RVEA_RERANK(MV) k_rerank<MV, false><<<blocks(R.M, kRows), 64, 0, s>>>(R, 1)
     RVEA_M_DISPATCH(R.m, RVEA_RERANK);
 #undef RVEA_RERANK
+    return hipGetLastError();
+}
+
+// gamma of Eq. 5 through the same two passes, rows = vectors
+hipError_t launch_gamma(const RunView &R, hipStream_t s, int force)
+{
+    constexpr int RR = 4;
+    const dim3 grid(blocks(R.K, 256 * RR), (unsigned)R.KC);
+#define RVEA_GA(MV) k_assoc<MV, RR, true><<<grid, 256, 0, s>>>(R, force)
+    RVEA_M_DISPATCH(R.m, RVEA_GA);
+#undef RVEA_GA
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define RVEA_GR(MV) k_rerank<MV, true><<<blocks(R.K, kRows), 64, 0, s>>>(R, force)
+    RVEA_M_DISPATCH(R.m, RVEA_GR);
+#undef RVEA_GR
     return hipGetLastError();
 }
 

@@ -3,9 +3,7 @@
 //               with H divisions, found by unranking the j-th (m-1)-subset
 //               of {1..H+m-1} in lexicographic order (parts a_i = c_i -
 //               c_{i-1} - 1, w = a/H), normalised to unit length
-//   k_gamma     Eq. 5: gamma_j = min over i != j of the angle between v_i and
-//               v_j, double precision, v_i.v_j / (|v_i| |v_j|) as an fma
-//               chain; exactly parallel vectors are skipped, pi/2 if none
+//   (gamma of Eq. 5 runs through the association kernels, k_select.hip)
 //   k_adapt_v   Alg. 2 line 8 (rule of the cited RVEA): V_j = V0_j o r /
 //               |V0_j o r| with r the survivors' per-objective range; left
 //               unchanged if some range is not positive and finite
@@ -73,51 +71,6 @@ __global__ void k_vec_aux(RunView R)
     write_aux(R, j, v);
 }
 
-template <int MD>
-__global__ __launch_bounds__(256) void k_gamma(RunView R, int force)
-{
-    if (!force && *R.vchanged == 0) return;
-    __shared__ double sv[256 * MD];
-    __shared__ double sn[256];
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double vj[MD];
-    double nj = 1.0;
-    if (j < R.K) {
-#pragma unroll
-        for (int k = 0; k < MD; ++k) vj[k] = R.V[j * MD + k];
-        nj = R.vn[j];
-    } else {
-#pragma unroll
-        for (int k = 0; k < MD; ++k) vj[k] = 0.0;
-    }
-    double best = -2.0;
-    bool found = false;
-    for (int64_t base = 0; base < R.K; base += 256) {
-        __syncthreads();
-        const int64_t ii = base + threadIdx.x;
-        if (ii < R.K) {
-#pragma unroll
-            for (int k = 0; k < MD; ++k) sv[threadIdx.x * MD + k] = R.V[ii * MD + k];
-            sn[threadIdx.x] = R.vn[ii];
-        }
-        __syncthreads();
-        const int cnt = (int)(R.K - base < 256 ? R.K - base : 256);
-        for (int q = 0; q < cnt; ++q) {
-            const int64_t i = base + q;
-            const double *vi = sv + q * MD;
-            double s = vi[0] * vj[0];
-#pragma unroll
-            for (int k = 1; k < MD; ++k) s = fma(vi[k], vj[k], s);
-            const double c = s / (sn[q] * nj);
-            if (i != j && c < 1.0 && (!found || c > best)) {
-                best = c;
-                found = true;
-            }
-        }
-    }
-    if (j < R.K) R.gamma[j] = found ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
-}
-
 __global__ void k_adapt_v(RunView R)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,20 +102,6 @@ __global__ void k_adapt_v(RunView R)
 
 // ------------------------------------------------------------- launchers
 static unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-hipError_t launch_gamma(const RunView &R, hipStream_t s, int force)
-{
-    switch (R.m) {
-    case 2: k_gamma<2><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
-    case 3: k_gamma<3><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
-    case 4: k_gamma<4><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
-    case 5: k_gamma<5><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
-    case 6: k_gamma<6><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
-    case 7: k_gamma<7><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
-    default: k_gamma<8><<<blocks(R.K, 256), 256, 0, s>>>(R, force); break;
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_lattice(const RunView &R, hipStream_t s, int H)
 {

@@ -42,7 +42,9 @@ struct RunView {
     int32_t *parents;   // ceil(N/2) x 2 slot indices
     int32_t *vs;        // K valid slots, ascending
     int32_t *nvalid;    // 1
-    int32_t *used;      // K+N physical-row flags
+    int32_t *stamp;     // K+N: generation that last found the row in use
+    int32_t *bcount;    // per-block valid-slot counts (prepare)
+    int32_t *freecnt;   // 1: free rows handed out (prepare)
     double *V0, *V;     // K x m
     float *V32;         // K x 4 or K x 8 (padded with zeros)
     double *vn;         // K norms of V
@@ -58,6 +60,7 @@ struct RunView {
     int64_t *t_done;    // completed generations
     unsigned long long *counters;  // 0 non-finite rows, 1 full rescans, 2 site overflow
     int32_t *vchanged;  // 1: adaptation changed V
+    double *pen;        // 1: m (t/t_max)^alpha of the current generation
 };
 
 // ---------------------------------------------------------------- Philox

@@ -29,8 +29,9 @@ struct Layout {
 
 enum Buf {
     B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_FN, B_ROWN, B_VALIDN, B_MVALID, B_PARENTS, B_VS,
-    B_NVALID, B_USED, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
-    B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_COUNT
+    B_NVALID, B_STAMP, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
+    B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_BCOUNT, B_FREECNT, B_PEN,
+    B_COUNT
 };
 
 int64_t binomial(int64_t n, int64_t k)
@@ -90,7 +91,8 @@ void make_layout(int m, int d, int64_t N, int64_t K, Layout &L)
         (size_t)P * 2 * 4, (size_t)K * 4, 4, (size_t)(K + N) * 4, (size_t)K * m * 8,
         (size_t)K * m * 8, (size_t)K * L.stride * 4, (size_t)K * 8, (size_t)K * 8,
         (size_t)m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
-        (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4};
+        (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4,
+        (size_t)((K + N + 255) / 256) * 4, 4, 8};
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -119,6 +121,11 @@ struct rvea_run_s {
     };
     std::vector<Ev> events;
     std::vector<hipEvent_t> pool;
+    // whole-generation graphs: [0] step+select, [1] step+select+adapt
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool use_graphs = true;
 };
 
 namespace {
@@ -288,7 +295,10 @@ rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_
     R.parents = (int32_t *)(w + L.off[B_PARENTS]);
     R.vs = (int32_t *)(w + L.off[B_VS]);
     R.nvalid = (int32_t *)(w + L.off[B_NVALID]);
-    R.used = (int32_t *)(w + L.off[B_USED]);
+    R.stamp = (int32_t *)(w + L.off[B_STAMP]);
+    R.bcount = (int32_t *)(w + L.off[B_BCOUNT]);
+    R.freecnt = (int32_t *)(w + L.off[B_FREECNT]);
+    R.pen = (double *)(w + L.off[B_PEN]);
     R.V0 = (double *)(w + L.off[B_V0]);
     R.V = (double *)(w + L.off[B_V]);
     R.V32 = (float *)(w + L.off[B_V32]);
@@ -308,6 +318,8 @@ rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_
 
     hipError_t e = hipMemsetAsync(R.counters, 0, 3 * sizeof(unsigned long long), r->stream);
     if (e == hipSuccess) e = hipMemsetAsync(R.vchanged, 0, 4, r->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(R.stamp, 0xff, (size_t)(K + N) * 4, r->stream);
     if (e == hipSuccess) e = launch_lattice(R, r->stream, r->H);
     if (e == hipSuccess) e = launch_gamma(R, r->stream, 1);
     if (e == hipSuccess) e = launch_init(R, r->stream);
@@ -359,9 +371,56 @@ rvea_status rvea_adapt(rvea_run r)
     return RVEA_OK;
 }
 
+namespace {
+
+// enqueue one generation's kernels on stream s (graph capture or eager)
+hipError_t enqueue_generation(const RunView &R, hipStream_t s, bool adapt)
+{
+    hipError_t e = launch_prepare(R, s);
+    if (e == hipSuccess) e = launch_offspring(R, s);
+    if (e == hipSuccess) e = launch_select_front(R, s);
+    if (e == hipSuccess) e = launch_assoc(R, s);
+    if (e == hipSuccess) e = launch_rerank(R, s);
+    if (e == hipSuccess) e = launch_select_back(R, s);
+    if (e == hipSuccess && adapt) e = launch_adapt(R, s);
+    return e;
+}
+
+rvea_status build_graphs(rvea_run r)
+{
+    if (r->gexec[0] && r->gexec[1]) return RVEA_OK;
+    if (!r->cap_stream)
+        HIPCHK(r, hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking));
+    for (int v = 0; v < 2; ++v) {
+        HIPCHK(r, hipStreamBeginCapture(r->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_generation(r->R, r->cap_stream, v == 1);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(r->cap_stream, &g);
+        if (e != hipSuccess) return fail(r, e, "graph capture");
+        if (e2 != hipSuccess) return fail(r, e2, "hipStreamEndCapture");
+        r->graph[v] = g;
+        HIPCHK(r, hipGraphInstantiate(&r->gexec[v], g, nullptr, nullptr, 0));
+    }
+    return RVEA_OK;
+}
+
+}  // namespace
+
 rvea_status rvea_run_generations(rvea_run r, int n)
 {
     if (!r || n < 0) return RVEA_EINVAL;
+    if (n > 0 && r->phase != 0) return RVEA_ESTATE;
+    if (r->use_graphs && r->timing == 0 && n > 0) {
+        rvea_status st = build_graphs(r);
+        if (st != RVEA_OK) return st;
+        for (int i = 0; i < n; ++i) {
+            const bool adapt = (r->t + 1) % r->R.period == 0;
+            HIPCHK(r, hipGraphLaunch(r->gexec[adapt ? 1 : 0], r->stream));
+            r->t += 1;
+        }
+        r->has_selection = true;
+        return RVEA_OK;
+    }
     for (int i = 0; i < n; ++i) {
         rvea_status st = rvea_step(r);
         if (st == RVEA_OK) st = rvea_select(r);
@@ -453,6 +512,7 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
     else if (V)
         HIPCHK(r, launch_gamma(R, r->stream, 1));
     HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemset(R.stamp, 0xff, (size_t)(R.K + R.N) * 4));
     HIPCHK(r, hipStreamSynchronize(r->stream));
     r->t = t;
     r->has_selection = false;
@@ -539,6 +599,13 @@ rvea_status rvea_get_counters(rvea_run r, rvea_counters *out)
     return RVEA_OK;
 }
 
+rvea_status rvea_set_graphs(rvea_run r, int enable)
+{
+    if (!r) return RVEA_EINVAL;
+    r->use_graphs = enable != 0;
+    return RVEA_OK;
+}
+
 rvea_status rvea_set_timing(rvea_run r, int kernel_mask)
 {
     if (!r) return RVEA_EINVAL;
@@ -579,6 +646,11 @@ rvea_status rvea_destroy(rvea_run r)
         (void)hipEventDestroy(ev.b);
     }
     for (auto e : r->pool) (void)hipEventDestroy(e);
+    for (int v = 0; v < 2; ++v) {
+        if (r->gexec[v]) (void)hipGraphExecDestroy(r->gexec[v]);
+        if (r->graph[v]) (void)hipGraphDestroy(r->graph[v]);
+    }
+    if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
     delete r;
     return RVEA_OK;
 }

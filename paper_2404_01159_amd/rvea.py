@@ -20,7 +20,8 @@ KERNEL_OFFSPRING, KERNEL_ASSOC, KERNEL_RERANK, KERNEL_GAMMA = 0, 1, 2, 3
 
 EXPORTS = [
     "rvea_default_params", "rvea_lattice_divisions", "rvea_footprint", "rvea_create",
-    "rvea_step", "rvea_select", "rvea_adapt", "rvea_run_generations", "rvea_get_state",
+    "rvea_step", "rvea_select", "rvea_adapt", "rvea_run_generations", "rvea_set_graphs",
+    "rvea_get_state",
     "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
     "rvea_get_counters",
     "rvea_set_timing", "rvea_kernel_time", "rvea_synchronize", "rvea_destroy",
@@ -59,6 +60,7 @@ def _load():
         "rvea_create": [i32, i32, i32, i64, i64, u64, P, P, sz, P, P],
         "rvea_step": [P], "rvea_select": [P], "rvea_adapt": [P],
         "rvea_run_generations": [P, i32],
+        "rvea_set_graphs": [P, i32],
         "rvea_get_state": [P, P, P, P, P, P, P, P],
         "rvea_set_state": [P, P, P, P, P, P, i64],
         "rvea_get_offspring": [P, P, P, P],
@@ -164,6 +166,9 @@ class Run:
 
     def run(self, n):
         self._chk(lib.rvea_run_generations(self._h, n), "rvea_run_generations")
+
+    def set_graphs(self, on):
+        self._chk(lib.rvea_set_graphs(self._h, 1 if on else 0), "rvea_set_graphs")
 
     def synchronize(self):
         self._chk(lib.rvea_synchronize(self._h), "rvea_synchronize")

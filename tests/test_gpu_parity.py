@@ -310,3 +310,23 @@ def test_kernel_timing_records_launches(P):
         assert n == 10 and ms > 0
     ms, n = run.kernel_time(3)
     assert n == 1
+
+
+def test_graph_replays_match_eager(P):
+    """Captured-graph generations equal eager ones, replay after replay, with
+    eager work and synchronizations between the replays."""
+    a = P.Run(1, 3, 200, 300, 300, seed=21, params=P.default_params(t_max=40))
+    b = P.Run(1, 3, 200, 300, 300, seed=21, params=P.default_params(t_max=40))
+    a.set_graphs(False)
+    for chunk in (7, 1, 5, 12):
+        a.run(chunk)
+        b.run(chunk)
+        sa, sb = a.get_state(), b.get_state()
+        for k in ("X", "F", "valid", "V", "gamma", "t"):
+            assert np.array_equal(sa[k], sb[k], equal_nan=True), (chunk, k)
+        # eager generation on both in between the replays
+        a.generation()
+        b.generation()
+        b.synchronize()
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa["X"], sb["X"]) and sa["t"] == sb["t"] == 29
