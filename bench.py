@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-kernel events (for profiler runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 5 times (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {a.gpus} is not supported by this build",
@@ -78,6 +81,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if a.calibrate_copy:
+        n = a.calibrate_copy * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 5}), flush=True)
+        return
 
     import paper_2404_01159_amd as P
     from workloads import CONFIGS

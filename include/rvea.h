@@ -29,7 +29,8 @@
  *   - Call order per generation: rvea_step, rvea_select, rvea_adapt.
  *     A call out of this order returns RVEA_ESTATE and enqueues nothing.
  *   - On RVEA_EDEVICE the HIP error text is available from
- *     rvea_last_error(run).
+ *     rvea_last_error(run); for a failed rvea_create, from
+ *     rvea_last_error(NULL) on the same thread.
  */
 #ifndef RVEA_H
 #define RVEA_H

@@ -20,36 +20,6 @@
 namespace rvea {
 
 // ------------------------------------------------------------------ scans
-// exclusive prefix sum over a 1024-thread block; returns the element's
-// offset and writes the block total to *total (every thread)
-__device__ int block_scan_1024(int v, int *total)
-{
-    __shared__ int wsum[16];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    if (wid == 0) {
-        int s = lane < 16 ? wsum[lane] : 0;
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            const int y = __shfl_up(s, o, 64);
-            if (lane >= o) s += y;
-        }
-        if (lane < 16) wsum[lane] = s;  // inclusive
-    }
-    __syncthreads();
-    const int before = wid > 0 ? wsum[wid - 1] : 0;
-    *total = wsum[15];
-    __syncthreads();
-    return before + x - v;
-}
-
 // Per generation, before the offspring: (1) every row a valid slot points
 // at is stamped with the generation number and each block of 256 slots
 // counts its valid slots; (2) each block adds the counts of the blocks
@@ -84,6 +54,19 @@ __global__ __launch_bounds__(256) void k_prep_count(RunView R)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int32_t gen = (int32_t)(*R.t_done + 1);
+    // reset the selection's per-vector minima for this generation
+    if (j < R.K) {
+        R.key[j] = ~0ull;
+        R.surv[j] = 0x7fffffff;
+    }
+    if (j < R.m) {
+        R.zbits[j] = 0xffffffffu;  // ideal point: encodes the largest value
+        R.rbits[j] = 0xffffffffu;  // survivors' minimum
+        R.rbits[R.m + j] = 0u;     // survivors' maximum
+    }
+    if (j == 0) {  // Eq. 4 penalty factor m (t/t_max)^alpha of this generation
+        *R.pen = (double)R.m * pow((double)gen / (double)R.t_max, R.alpha);
+    }
     int v = 0;
     if (j < R.K && R.valid[j]) {
         v = 1;
@@ -154,6 +137,60 @@ __device__ __forceinline__ double recip(double z)
     return r;
 }
 
+// a^(-1/n), a in (0, 2], n a positive integer: single-precision estimate and
+// two Newton steps on z^-n = a (z <- z (1 + (1 - a z^n)/n)), error
+// ~ (n+1)/2 e^2 per step, leaving a few binary64 ulps
+__device__ __forceinline__ double inv_root(double a, int n)
+{
+    const float ninv = 1.0f / (float)n;
+    double z = (double)exp2f(-log2f((float)a) * ninv);
+    const double dn = 1.0 / (double)n;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-a, ipow(z, n), 1.0);
+        z = fma(z * e, dn, z);
+    }
+    return z;
+}
+
+// polynomial mutation shift Delta of Appendix B, binary64:
+//   M < 1/2: (ub-lb) [(2M + (1-2M)(1-d1)^(xi+1))^(1/(xi+1)) - 1]
+//   M > 1/2: (ub-lb) [1 - (2(1-M) + 2(M-1/2)(1-d2)^(xi+1))^(1/(xi+1))]
+// d1 = (x-lb)/(ub-lb), d2 = (ub-x)/(ub-lb).  For integer n = xi+1 the
+// power is a product and the root the Newton root above; otherwise pow().
+__device__ __attribute__((noinline)) double pm_delta_pow(double x, double lb, double ub,
+                                                        double mm, double xi)
+{
+    const double span = ub - lb;
+    const double e = 1.0 / (xi + 1.0);
+    if (mm < 0.5) {
+        const double d1 = (x - lb) / span;
+        const double base = 2.0 * mm + (1.0 - 2.0 * mm) * pow(1.0 - d1, xi + 1.0);
+        return span * (pow(base, e) - 1.0);
+    }
+    if (mm > 0.5) {
+        const double d2 = (ub - x) / span;
+        const double base = 2.0 * (1.0 - mm) + 2.0 * (mm - 0.5) * pow(1.0 - d2, xi + 1.0);
+        return span * (1.0 - pow(base, e));
+    }
+    return 0.0;
+}
+
+__device__ __forceinline__ double pm_delta(double x, double lb, double ub, double mm, double xi,
+                                           int n)
+{
+    if (n <= 0) return pm_delta_pow(x, lb, ub, mm, xi);
+    if (mm == 0.5) return 0.0;
+    const double span = ub - lb;
+    const bool lo = mm < 0.5;
+    const double dd = lo ? (x - lb) / span : (ub - x) / span;
+    const double base = lo ? 2.0 * mm + (1.0 - 2.0 * mm) * ipow(1.0 - dd, n)
+                           : 2.0 * (1.0 - mm) + 2.0 * (mm - 0.5) * ipow(1.0 - dd, n);
+    if (base > 0.0 && base < 1e-30) return pm_delta_pow(x, lb, ub, mm, xi);  // below float range
+    const double r = base > 0.0 ? recip(inv_root(base, n)) : 0.0;
+    return lo ? span * (r - 1.0) : span * (1.0 - r);
+}
+
 __device__ __attribute__((noinline)) double sbx_beta_pow(double mc, double eta)
 {
     const double e = 1.0 / (eta + 1.0);
@@ -172,37 +209,10 @@ __device__ __forceinline__ double sbx_beta(double mc, double eta, int n)
     if (n > 0) {
         if (mc == 0.0) return 0.0;
         const double a = mc < 0.5 ? 2.0 * mc : 2.0 - 2.0 * mc;
-        const float ninv = 1.0f / (float)n;
-        double z = (double)exp2f(-log2f((float)a) * ninv);
-        const double dn = 1.0 / (double)n;
-#pragma unroll
-        for (int it = 0; it < 2; ++it) {
-            const double e = fma(-a, ipow(z, n), 1.0);
-            z = fma(z * e, dn, z);
-        }
+        const double z = inv_root(a, n);
         return mc < 0.5 ? recip(z) : z;
     }
     return sbx_beta_pow(mc, eta);
-}
-
-// rare (about one site per child): kept out of line so it does not raise the
-// register budget of the gene loop
-__device__ __attribute__((noinline)) double pm_delta(double x, double lb, double ub, double mm,
-                                                    double xi)
-{
-    const double span = ub - lb;
-    const double e = 1.0 / (xi + 1.0);
-    if (mm < 0.5) {
-        const double d1 = (x - lb) / span;
-        const double base = 2.0 * mm + (1.0 - 2.0 * mm) * pow(1.0 - d1, xi + 1.0);
-        return span * (pow(base, e) - 1.0);
-    }
-    if (mm > 0.5) {
-        const double d2 = (ub - x) / span;
-        const double base = 2.0 * (1.0 - mm) + 2.0 * (mm - 0.5) * pow(1.0 - d2, xi + 1.0);
-        return span * (1.0 - pow(base, e));
-    }
-    return 0.0;
 }
 
 // Sum over the S lanes of a segment (S a power of two <= 64).
@@ -397,6 +407,8 @@ __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
     const double lb = R.lb, ub = R.ub;
     const double np1 = R.eta_c + 1.0;
     const int nroot = (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
+    const double nm1 = R.eta_m + 1.0;
+    const int nroot_m = (nm1 >= 1.0 && nm1 <= 64.0 && nm1 == (double)(int)nm1) ? (int)nm1 : 0;
     double g1 = 0.0, g2 = 0.0;
     float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
 
@@ -422,10 +434,10 @@ __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
             const int g = g0 + k;
             for (int s_ = 0; s_ < n1; ++s_)
                 if (sh_sites[seg][0][s_] == g)
-                    c1 = dclip(c1 + pm_delta(c1, lb, ub, sh_mags[seg][0][s_], R.eta_m), lb, ub);
+                    c1 = dclip(c1 + pm_delta(c1, lb, ub, sh_mags[seg][0][s_], R.eta_m, nroot_m), lb, ub);
             for (int s_ = 0; s_ < n2; ++s_)
                 if (sh_sites[seg][1][s_] == g)
-                    c2 = dclip(c2 + pm_delta(c2, lb, ub, sh_mags[seg][1][s_], R.eta_m), lb, ub);
+                    c2 = dclip(c2 + pm_delta(c2, lb, ub, sh_mags[seg][1][s_], R.eta_m, nroot_m), lb, ub);
             y1[k] = (float)c1;
             y2[k] = (float)c2;
             if (g < R.d && g >= R.m - 1) {

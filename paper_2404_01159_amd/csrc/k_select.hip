@@ -23,24 +23,6 @@
 
 namespace rvea {
 
-__global__ void k_sel_reset(RunView R)
-{
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) {  // Eq. 4 penalty factor m (t/t_max)^alpha of this generation
-        const double tcur = (double)(*R.t_done + 1);
-        *R.pen = (double)R.m * pow(tcur / (double)R.t_max, R.alpha);
-    }
-    if (j < R.K) {
-        R.key[j] = ~0ull;
-        R.surv[j] = 0x7fffffff;
-    }
-    if (j < R.m) {
-        R.zbits[j] = 0xffffffffu;     // encodes the largest value
-        R.rbits[j] = 0xffffffffu;     // survivor minimum
-        R.rbits[R.m + j] = 0u;        // survivor maximum
-    }
-}
-
 // wave-wide minimum / maximum of an ordered encoding
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 {
@@ -522,8 +504,6 @@ static unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_select_front(const RunView &R, hipStream_t s)
 {
-    const int64_t n = R.K > R.m ? R.K : R.m;
-    k_sel_reset<<<blocks(n, 256), 256, 0, s>>>(R);
     k_ideal<<<blocks(R.M, 256), 256, 0, s>>>(R);
     return hipGetLastError();
 }

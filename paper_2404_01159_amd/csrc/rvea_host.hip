@@ -130,6 +130,9 @@ struct rvea_run_s {
 
 namespace {
 
+// message of the last failed rvea_create on this thread (no handle exists)
+thread_local char g_create_err[512] = "";
+
 rvea_status fail(rvea_run r, hipError_t e, const char *what)
 {
     if (r) std::snprintf(r->err, sizeof r->err, "%s: %s", what, hipGetErrorString(e));
@@ -324,10 +327,12 @@ rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_
     if (e == hipSuccess) e = launch_gamma(R, r->stream, 1);
     if (e == hipSuccess) e = launch_init(R, r->stream);
     if (e != hipSuccess) {
-        fail(r, e, "initialization");
+        std::snprintf(g_create_err, sizeof g_create_err, "initialization: %s (%d)",
+                      hipGetErrorString(e), (int)e);
         delete r;
         return RVEA_EDEVICE;
     }
+    g_create_err[0] = 0;
     *out = r;
     return RVEA_OK;
 }
@@ -668,6 +673,10 @@ const char *rvea_status_str(rvea_status s)
     return "unknown status";
 }
 
-const char *rvea_last_error(rvea_run r) { return r ? r->err : "no run"; }
+const char *rvea_last_error(rvea_run r)
+{
+    if (r) return r->err;
+    return g_create_err[0] ? g_create_err : "no run";
+}
 
 }  // extern "C"

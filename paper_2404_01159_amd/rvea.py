@@ -10,6 +10,8 @@ import ctypes as C
 import os
 
 import numpy as np
+import torch  # noqa: F401  -- load torch's HIP runtime first: librvea.so binds to it
+
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librvea.so")
@@ -121,8 +123,6 @@ class Run:
 
     def __init__(self, problem, m, d, N, K, seed=0, params=None, device="cuda:0",
                  stream=None, workspace=None):
-        import torch
-
         self.problem, self.m, self.d, self.N, self.K = problem, m, d, N, K
         self.M = K + N
         self.seed = seed
@@ -142,7 +142,8 @@ class Run:
                                  C.c_void_p(aligned), avail, C.c_void_p(self.stream.cuda_stream),
                                  C.byref(self._h))
         if st != RVEA_OK:
-            raise RveaError(st, "rvea_create: " + lib.rvea_status_str(st).decode())
+            raise RveaError(st, "rvea_create: " + lib.rvea_status_str(st).decode() + ": "
+                            + lib.rvea_last_error(None).decode())
 
     # ------------------------------------------------------------------
     def _chk(self, st, what):
