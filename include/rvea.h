@@ -185,6 +185,35 @@ rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *laun
 rvea_status rvea_synchronize(rvea_run run);
 rvea_status rvea_destroy(rvea_run run);
 
+/* ---------------------------------------------------------------- batches
+ * A batch advances many independent runs (any problem, m, d, N, K) one
+ * generation per rvea_batch_step: each phase of the generation is one launch
+ * covering every admitted run (runs grouped by segment width or objective
+ * count), and the launch sequence is captured into one HIP graph that is
+ * replayed until the membership changes.  Each run keeps its own workspace,
+ * state and Philox stream, so a run's results do not depend on what else is
+ * in the batch.  Adaptation is decided on the device per run.
+ *   workspace   device memory of rvea_batch_footprint(max_runs) bytes,
+ *               256-byte aligned, owned by the caller (run table and spans)
+ *   hip_stream  the stream every batched generation is enqueued on
+ * While admitted, a run rejects rvea_step/select/adapt/run_generations and
+ * rvea_set_state (RVEA_ESTATE); its accessors wait for the batch stream.
+ * Admission needs the run between generations and timing off; it fails with
+ * RVEA_ENOMEM when max_runs runs are admitted. */
+typedef struct rvea_batch_s *rvea_batch;
+rvea_status rvea_batch_footprint(int max_runs, size_t *bytes);
+rvea_status rvea_batch_create(int max_runs, void *workspace, size_t workspace_bytes,
+                              void *hip_stream, rvea_batch *out);
+rvea_status rvea_batch_admit(rvea_batch batch, rvea_run run);
+rvea_status rvea_batch_retire(rvea_batch batch, rvea_run run);
+rvea_status rvea_batch_step(rvea_batch batch);
+/* 1 (default) = replay captured graphs once the membership is stable. */
+rvea_status rvea_batch_set_graphs(rvea_batch batch, int enable);
+rvea_status rvea_batch_size(rvea_batch batch, int *n);
+rvea_status rvea_batch_synchronize(rvea_batch batch);
+rvea_status rvea_batch_destroy(rvea_batch batch);
+const char *rvea_batch_last_error(rvea_batch batch);
+
 const char *rvea_status_str(rvea_status s);
 const char *rvea_last_error(rvea_run run);
 

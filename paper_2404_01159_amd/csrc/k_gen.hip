@@ -50,9 +50,9 @@ __device__ __forceinline__ int block_scan_256(int v, int *total)
     return before + x - v;
 }
 
-__global__ __launch_bounds__(256) void k_prep_count(RunView R)
+__device__ __forceinline__ void prep_count_body(const RunView &R, int64_t bx)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     const int32_t gen = (int32_t)(*R.t_done + 1);
     // reset the selection's per-vector minima for this generation
     if (j < R.K) {
@@ -77,18 +77,18 @@ __global__ __launch_bounds__(256) void k_prep_count(RunView R)
     if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(b);
     __syncthreads();
     if (threadIdx.x == 0) {
-        R.bcount[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
-        if (blockIdx.x == 0) *R.freecnt = 0;
+        R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
+        if (bx == 0) *R.freecnt = 0;
     }
 }
 
-__global__ __launch_bounds__(256) void k_prep_write(RunView R)
+__device__ __forceinline__ void prep_write_body(const RunView &R, int64_t bx)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     const int32_t gen = (int32_t)(*R.t_done + 1);
     // offset of this block's valid slots
     int pre = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) pre += R.bcount[b];
+    for (int b = threadIdx.x; b < (int)bx; b += 256) pre += R.bcount[b];
     int dummy;
     const int zero = block_scan_256(pre, &dummy);
     (void)zero;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_prep_write(RunView R)
     const int pos = block_scan_256(v, &tot);
     if (v) R.vs[offset + pos] = (int32_t)j;
     const int64_t nblk = (R.K + 255) / 256;
-    if ((int64_t)blockIdx.x == nblk - 1 && threadIdx.x == 0) *R.nvalid = offset + tot;
+    if (bx == nblk - 1 && threadIdx.x == 0) *R.nvalid = offset + tot;
     // free rows of this block
     const int fr = (j < R.K + R.N && R.stamp[j] != gen) ? 1 : 0;
     int ftot;
@@ -108,6 +108,9 @@ __global__ __launch_bounds__(256) void k_prep_write(RunView R)
     __syncthreads();
     if (fr && fbase + fpos < R.N) R.off_row[fbase + fpos] = (int32_t)j;
 }
+
+__global__ __launch_bounds__(256) void k_prep_count(RunView R) { prep_count_body(R, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_prep_write(RunView R) { prep_write_body(R, blockIdx.x); }
 
 // --------------------------------------------------------------- helpers
 // z^n for a positive integer n (square and multiply, n uniform); the
@@ -345,7 +348,7 @@ __device__ void draw_sites(const RunView &R, uint32_t t, int64_t o1, int64_t o2,
 }
 
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
+__device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
 {
     constexpr int SEGS = kBlock / S;
     __shared__ int32_t sh_sites[SEGS][2][kMaxSites];
@@ -353,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
 
     const int seg = threadIdx.x / S, lane = threadIdx.x % S;
     const int64_t P = (R.N + 1) / 2;
-    const int64_t p = (int64_t)blockIdx.x * SEGS + seg;
+    const int64_t p = bx * SEGS + seg;
     const bool active = p < P;
     const uint32_t t = (uint32_t)(*R.t_done + 1);
     const int64_t o1 = p, o2 = p + P;
@@ -476,6 +479,30 @@ __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
     }
 }
 
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
+{
+    offspring_body<S>(R, blockIdx.x);
+}
+
+// ----------------------------------------------------- batched (many runs)
+__global__ __launch_bounds__(256) void kb_prep_count(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    prep_count_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+__global__ __launch_bounds__(256) void kb_prep_write(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    prep_write_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+template <int S>
+__global__ __launch_bounds__(kBlock) void kb_offspring(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    offspring_body<S>(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+
 // ------------------------------------------------------------- launchers
 int pick_segment(int d)
 {
@@ -501,6 +528,27 @@ int pick_segment(int d)
             break;                                                                           \
         }                                                                                    \
     } while (0)
+
+hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span *sp, int n,
+                            int64_t blocks, hipStream_t s)
+{
+    const dim3 g((unsigned)blocks);
+    switch (phase) {
+    case BP_PREP_COUNT: kb_prep_count<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_PREP_WRITE: kb_prep_write<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_OFFSPRING:
+        switch (cls) {
+        case 4: kb_offspring<4><<<g, kBlock, 0, s>>>(runs, sp, n); break;
+        case 8: kb_offspring<8><<<g, kBlock, 0, s>>>(runs, sp, n); break;
+        case 16: kb_offspring<16><<<g, kBlock, 0, s>>>(runs, sp, n); break;
+        case 32: kb_offspring<32><<<g, kBlock, 0, s>>>(runs, sp, n); break;
+        default: kb_offspring<64><<<g, kBlock, 0, s>>>(runs, sp, n); break;
+        }
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_init(const RunView &R, hipStream_t s)
 {

@@ -38,12 +38,12 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 }
 
 // rows that take part: valid parent slots and all offspring with finite F
-__global__ __launch_bounds__(256) void k_ideal(RunView R)
+__device__ __forceinline__ void ideal_body(const RunView &R, int64_t bx)
 {
     __shared__ uint32_t smin[kMaxM];
     if (threadIdx.x < kMaxM) smin[threadIdx.x] = 0xffffffffu;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = bx * 256 + threadIdx.x;
     bool ok = false;
     if (i < R.M) {
         ok = i >= R.K || R.valid[i];
@@ -85,12 +85,11 @@ __device__ __forceinline__ float dotf(const float *f, const float4 *v)
 // GAMMA = true:  rows are the reference vectors themselves (Eq. 5), with the
 // pair (j, j) excluded.
 template <int MD, int RR, bool GAMMA>
-__global__ __launch_bounds__(256) void k_assoc(RunView R, int gate)
+__device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, int gate)
 {
     if (GAMMA && !gate && *R.vchanged == 0) return;  // uniform: vectors unchanged
     constexpr int NV4 = MD <= 4 ? 1 : 2;  // float4 per vector
     __shared__ float4 sv[1024 * NV4];
-    const int c = blockIdx.y;
     const int64_t j0 = (int64_t)c * R.CS;
     const int64_t left = R.K - j0;
     const int nvec = (int)(left < R.CS ? left : R.CS);
@@ -111,7 +110,7 @@ __global__ __launch_bounds__(256) void k_assoc(RunView R, int gate)
     int64_t rows[RR];
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
-        const int64_t i = (int64_t)blockIdx.x * (256 * RR) + r * 256 + threadIdx.x;
+        const int64_t i = bx * (256 * RR) + r * 256 + threadIdx.x;
         rows[r] = i;
         const bool ok = i < nrows && (GAMMA || R.mvalid[i]);
         float n2 = 0.f;
@@ -201,7 +200,7 @@ constexpr int kItems = 8;
 constexpr int kRows = 16;  // rows per wave
 
 template <int MD, bool GAMMA>
-__global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
+__device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int gate)
 {
     if (GAMMA && !gate && *R.vchanged == 0) return;  // uniform: vectors unchanged
     __shared__ double s_f[kRows][MD];
@@ -214,7 +213,7 @@ __global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
 
     const int t = threadIdx.x;
     const int r = t >> 2, sub = t & 3;
-    const int64_t base = (int64_t)blockIdx.x * kRows;
+    const int64_t base = bx * kRows;
     const int64_t i = base + r;
     const int64_t nrows = GAMMA ? R.K : R.M;
 
@@ -433,9 +432,9 @@ __global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
     atomicMin(&R.key[bj], (unsigned long long)__double_as_longlong(a));
 }
 
-__global__ void k_surv(RunView R)
+__device__ __forceinline__ void surv_body(const RunView &R, int64_t bx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = bx * 256 + threadIdx.x;
     if (i >= R.M) return;
     const int32_t j = R.assoc[i];
     if (j < 0) return;
@@ -443,9 +442,9 @@ __global__ void k_surv(RunView R)
         atomicMin(&R.surv[j], (int32_t)i);
 }
 
-__global__ void k_newpop(RunView R)
+__device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     if (j >= R.K) return;
     const int32_t s = R.surv[j];
     if (s == 0x7fffffff) {
@@ -462,7 +461,7 @@ __global__ void k_newpop(RunView R)
 
 // commit the new population and count the generation; also reduce the
 // survivors' per-objective extremes for a possible adaptation
-__global__ __launch_bounds__(256) void k_commit(RunView R)
+__device__ __forceinline__ void commit_body(const RunView &R, int64_t bx)
 {
     __shared__ uint32_t smin[kMaxM], smax[kMaxM];
     if (threadIdx.x < kMaxM) {
@@ -470,7 +469,7 @@ __global__ __launch_bounds__(256) void k_commit(RunView R)
         smax[threadIdx.x] = 0u;
     }
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     uint8_t v = 0;
     if (j < R.K) {
         v = R.valid_n[j];
@@ -496,7 +495,61 @@ __global__ __launch_bounds__(256) void k_commit(RunView R)
         if (smin[threadIdx.x] != 0xffffffffu) atomicMin(&R.rbits[threadIdx.x], smin[threadIdx.x]);
         atomicMax(&R.rbits[R.m + threadIdx.x], smax[threadIdx.x]);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *R.t_done += 1;
+    if (bx == 0 && threadIdx.x == 0) *R.t_done += 1;
+}
+
+// ------------------------------------------------------- single-run kernels
+__global__ __launch_bounds__(256) void k_ideal(RunView R) { ideal_body(R, blockIdx.x); }
+template <int MD, int RR, bool GAMMA>
+__global__ __launch_bounds__(256) void k_assoc(RunView R, int gate)
+{
+    assoc_body<MD, RR, GAMMA>(R, blockIdx.x, blockIdx.y, gate);
+}
+template <int MD, bool GAMMA>
+__global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
+{
+    rerank_body<MD, GAMMA>(R, blockIdx.x, gate);
+}
+__global__ __launch_bounds__(256) void k_surv(RunView R) { surv_body(R, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_newpop(RunView R) { newpop_body(R, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_commit(RunView R) { commit_body(R, blockIdx.x); }
+
+// ----------------------------------------------------- batched (many runs)
+// blockIdx.x is decoded into (run, local block) through the span table; for
+// the association, local = chunk * row_blocks + row_block.
+__global__ __launch_bounds__(256) void kb_ideal(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    ideal_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+template <int MD, int RR, bool GAMMA>
+__global__ __launch_bounds__(256) void kb_assoc(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    const int64_t local = blockIdx.x - sp[s].start;
+    const int64_t nbx = sp[s].nbx;
+    assoc_body<MD, RR, GAMMA>(runs[sp[s].run], local % nbx, (int)(local / nbx), 0);
+}
+template <int MD, bool GAMMA>
+__global__ __launch_bounds__(64) void kb_rerank(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    rerank_body<MD, GAMMA>(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+}
+__global__ __launch_bounds__(256) void kb_surv(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    surv_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+__global__ __launch_bounds__(256) void kb_newpop(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    newpop_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+__global__ __launch_bounds__(256) void kb_commit(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    commit_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 
 // ------------------------------------------------------------- launchers
@@ -562,5 +615,40 @@ hipError_t launch_select_back(const RunView &R, hipStream_t s)
 }
 
 int assoc_rows_per_block() { return 256 * 4; }
+
+hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Span *sp, int n,
+                               int64_t blocks, hipStream_t s)
+{
+    constexpr int RR = 4;
+    const dim3 g((unsigned)blocks);
+    switch (phase) {
+    case BP_IDEAL: kb_ideal<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_SURV: kb_surv<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_NEWPOP: kb_newpop<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_COMMIT: kb_commit<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_ASSOC:
+#define RVEA_BA(MV) kb_assoc<MV, RR, false><<<g, 256, 0, s>>>(runs, sp, n)
+        RVEA_M_DISPATCH(cls, RVEA_BA);
+#undef RVEA_BA
+        break;
+    case BP_RERANK:
+#define RVEA_BR(MV) kb_rerank<MV, false><<<g, 64, 0, s>>>(runs, sp, n)
+        RVEA_M_DISPATCH(cls, RVEA_BR);
+#undef RVEA_BR
+        break;
+    case BP_GAMMA_ASSOC:
+#define RVEA_BGA(MV) kb_assoc<MV, RR, true><<<g, 256, 0, s>>>(runs, sp, n)
+        RVEA_M_DISPATCH(cls, RVEA_BGA);
+#undef RVEA_BGA
+        break;
+    case BP_GAMMA_RERANK:
+#define RVEA_BGR(MV) kb_rerank<MV, true><<<g, 64, 0, s>>>(runs, sp, n)
+        RVEA_M_DISPATCH(cls, RVEA_BGR);
+#undef RVEA_BGR
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 }  // namespace rvea

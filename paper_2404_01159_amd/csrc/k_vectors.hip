@@ -71,12 +71,14 @@ __global__ void k_vec_aux(RunView R)
     write_aux(R, j, v);
 }
 
-__global__ void k_adapt_v(RunView R)
+// check_due: decide on the device whether this generation adapts (batched
+// runs advance in lockstep but joined at different generations)
+__device__ __forceinline__ void adapt_v_body(const RunView &R, int64_t bx, bool check_due)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     double r[kMaxM];
-    bool ok = true;
-    for (int k = 0; k < R.m; ++k) {
+    bool ok = !check_due || (*R.t_done % R.period) == 0;
+    for (int k = 0; k < R.m && ok; ++k) {
         const uint32_t lo = R.rbits[k], hi = R.rbits[R.m + k];
         if (lo == 0xffffffffu) {
             ok = false;
@@ -100,6 +102,14 @@ __global__ void k_adapt_v(RunView R)
     write_aux(R, j, v);
 }
 
+__global__ void k_adapt_v(RunView R) { adapt_v_body(R, blockIdx.x, false); }
+
+__global__ __launch_bounds__(256) void kb_adapt_v(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    adapt_v_body(runs[sp[s].run], blockIdx.x - sp[s].start, true);
+}
+
 // ------------------------------------------------------------- launchers
 static unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -113,6 +123,61 @@ hipError_t launch_vec_aux(const RunView &R, hipStream_t s)
 {
     k_vec_aux<<<blocks(R.K, 256), 256, 0, s>>>(R);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_vectors(int phase, int cls, const RunView *runs, const Span *sp, int n,
+                                int64_t blocks, hipStream_t s)
+{
+    (void)cls;
+    if (phase != BP_ADAPT) return hipErrorInvalidValue;
+    kb_adapt_v<<<dim3((unsigned)blocks), 256, 0, s>>>(runs, sp, n);
+    return hipGetLastError();
+}
+
+// block counts and template classes of the batched phases
+int batch_phase_class(int phase, const RunView &R)
+{
+    if (phase == BP_OFFSPRING) return pick_segment(R.d);
+    if (phase == BP_ASSOC || phase == BP_RERANK || phase == BP_GAMMA_ASSOC ||
+        phase == BP_GAMMA_RERANK)
+        return R.m;
+    return 0;
+}
+
+int64_t batch_phase_nbx(int phase, const RunView &R)
+{
+    const int64_t rows = phase == BP_GAMMA_ASSOC ? R.K : R.M;
+    return (rows + assoc_rows_per_block() - 1) / assoc_rows_per_block();
+}
+
+int64_t batch_phase_blocks(int phase, const RunView &R)
+{
+    switch (phase) {
+    case BP_PREP_COUNT:
+    case BP_PREP_WRITE: return (R.K + R.N + 255) / 256;
+    case BP_OFFSPRING: {
+        const int S = pick_segment(R.d);
+        return ((R.N + 1) / 2 + (kBlock / S) - 1) / (kBlock / S);
+    }
+    case BP_IDEAL:
+    case BP_SURV: return (R.M + 255) / 256;
+    case BP_ASSOC:
+    case BP_GAMMA_ASSOC: return batch_phase_nbx(phase, R) * R.KC;
+    case BP_RERANK: return (R.M + 15) / 16;
+    case BP_GAMMA_RERANK: return (R.K + 15) / 16;
+    case BP_NEWPOP:
+    case BP_COMMIT:
+    case BP_ADAPT: return (R.K + 255) / 256;
+    }
+    return 0;
+}
+
+hipError_t launch_batch(int phase, int cls, const RunView *runs, const Span *sp, int n,
+                        int64_t blocks, hipStream_t s)
+{
+    if (phase <= BP_OFFSPRING) return launch_batch_gen(phase, cls, runs, sp, n, blocks, s);
+    if (phase == BP_ADAPT) return launch_batch_vectors(phase, cls, runs, sp, n, blocks, s);
+    return launch_batch_select(phase, cls, runs, sp, n, blocks, s);
 }
 
 hipError_t launch_adapt(const RunView &R, hipStream_t s)

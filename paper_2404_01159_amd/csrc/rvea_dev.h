@@ -63,6 +63,26 @@ struct RunView {
     double *pen;        // 1: m (t/t_max)^alpha of the current generation
 };
 
+// One run's share of a batched launch: blocks [start, next start) belong to
+// run `run` of the device run table; nbx is the row-block count of a 2-D
+// (row block x vector chunk) phase.
+struct Span {
+    int64_t start;
+    int32_t run;
+    int32_t nbx;
+};
+
+// index of the span holding block b (spans sorted by start, first start 0)
+__device__ __forceinline__ int find_span(const Span *sp, int n, int64_t b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sp[mid].start <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------- Philox
 struct W4 {
     uint32_t w[4];

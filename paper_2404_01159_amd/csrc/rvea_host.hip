@@ -126,6 +126,29 @@ struct rvea_run_s {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool use_graphs = true;
+    rvea_batch batch = nullptr;  // non-null while admitted to a batch
+};
+
+struct rvea_batch_s {
+    int max_runs;
+    hipStream_t stream;
+    RunView *d_runs;  // max_runs views, device
+    Span *d_spans;    // BP_COUNT * max_runs spans, device
+    std::vector<rvea_run> runs;
+    struct Launch {
+        int phase, cls;
+        int64_t span_off;
+        int n;
+        int64_t blocks;
+    };
+    std::vector<Launch> plan;
+    bool dirty = true;
+    int64_t version = 0, graph_version = -1, last_step_version = -1;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool use_graphs = true;
+    char err[512] = "";
 };
 
 namespace {
@@ -340,7 +363,7 @@ rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_
 rvea_status rvea_step(rvea_run r)
 {
     if (!r) return RVEA_EINVAL;
-    if (r->phase != 0) return RVEA_ESTATE;
+    if (r->phase != 0 || r->batch) return RVEA_ESTATE;
     HIPCHK(r, launch_prepare(r->R, r->stream));
     rvea_status st = timed(r, 0, [&] { return launch_offspring(r->R, r->stream); }, "offspring");
     if (st != RVEA_OK) return st;
@@ -414,7 +437,7 @@ rvea_status build_graphs(rvea_run r)
 rvea_status rvea_run_generations(rvea_run r, int n)
 {
     if (!r || n < 0) return RVEA_EINVAL;
-    if (n > 0 && r->phase != 0) return RVEA_ESTATE;
+    if (n > 0 && (r->phase != 0 || r->batch)) return RVEA_ESTATE;
     if (r->use_graphs && r->timing == 0 && n > 0) {
         rvea_status st = build_graphs(r);
         if (st != RVEA_OK) return st;
@@ -435,10 +458,12 @@ rvea_status rvea_run_generations(rvea_run r, int n)
     return RVEA_OK;
 }
 
+static hipStream_t active_stream(rvea_run r) { return r->batch ? r->batch->stream : r->stream; }
+
 rvea_status rvea_synchronize(rvea_run r)
 {
     if (!r) return RVEA_EINVAL;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     return check_counters(r);
 }
 
@@ -470,7 +495,7 @@ rvea_status rvea_get_state(rvea_run r, float *X, float *F, uint8_t *valid, doubl
 {
     if (!r) return RVEA_EINVAL;
     const RunView &R = r->R;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     std::vector<uint8_t> vh(R.K);
     HIPCHK(r, hipMemcpy(vh.data(), R.valid, R.K, hipMemcpyDeviceToHost));
     if (valid) std::memcpy(valid, vh.data(), R.K);
@@ -494,9 +519,9 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
                            const double *V, const double *gamma, int64_t t)
 {
     if (!r || !X || !F || !valid || t < 0) return RVEA_EINVAL;
-    if (r->phase != 0) return RVEA_ESTATE;
+    if (r->phase != 0 || r->batch) return RVEA_ESTATE;
     const RunView &R = r->R;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     HIPCHK(r, hipMemcpy2D(R.X, (size_t)R.ld * 4, X, (size_t)R.d * 4, (size_t)R.d * 4,
                           (size_t)R.K, hipMemcpyHostToDevice));
     std::vector<int32_t> rows(R.K);
@@ -518,7 +543,7 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
         HIPCHK(r, launch_gamma(R, r->stream, 1));
     HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemset(R.stamp, 0xff, (size_t)(R.K + R.N) * 4));
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     r->t = t;
     r->has_selection = false;
     return RVEA_OK;
@@ -529,7 +554,7 @@ rvea_status rvea_get_offspring(rvea_run r, float *X, float *F, int32_t *parents)
     if (!r) return RVEA_EINVAL;
     if (r->phase == 0) return RVEA_ESTATE;
     const RunView &R = r->R;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     if (X) {
         std::vector<int32_t> rows(R.N);
         HIPCHK(r, hipMemcpy(rows.data(), R.off_row, R.N * 4, hipMemcpyDeviceToHost));
@@ -551,7 +576,7 @@ rvea_status rvea_get_selection(rvea_run r, float *zstar, int32_t *assoc, double 
     if (!r) return RVEA_EINVAL;
     if (!r->has_selection || r->phase == 1) return RVEA_ESTATE;
     const RunView &R = r->R;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     if (zstar) {
         uint32_t zb[kMaxM];
         HIPCHK(r, hipMemcpy(zb, R.zbits, R.m * 4, hipMemcpyDeviceToHost));
@@ -576,7 +601,7 @@ rvea_status rvea_get_rows(rvea_run r, int offspring, const int64_t *idx, int64_t
     const int64_t lim = offspring ? R.N : R.K;
     for (int64_t q = 0; q < n; ++q)
         if (idx[q] < 0 || idx[q] >= lim) return RVEA_EINVAL;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     std::vector<int32_t> map(lim);
     HIPCHK(r, hipMemcpy(map.data(), offspring ? R.off_row : R.slot_row, lim * 4,
                         hipMemcpyDeviceToHost));
@@ -596,7 +621,7 @@ rvea_status rvea_get_counters(rvea_run r, rvea_counters *out)
 {
     if (!r || !out) return RVEA_EINVAL;
     unsigned long long c[3];
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     HIPCHK(r, hipMemcpy(c, r->R.counters, sizeof c, hipMemcpyDeviceToHost));
     out->nonfinite_rows = (int64_t)c[0];
     out->full_rescans = (int64_t)c[1];
@@ -614,7 +639,7 @@ rvea_status rvea_set_graphs(rvea_run r, int enable)
 rvea_status rvea_set_timing(rvea_run r, int kernel_mask)
 {
     if (!r) return RVEA_EINVAL;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     for (auto &ev : r->events) {
         r->pool.push_back(ev.a);
         r->pool.push_back(ev.b);
@@ -627,7 +652,7 @@ rvea_status rvea_set_timing(rvea_run r, int kernel_mask)
 rvea_status rvea_kernel_time(rvea_run r, int kernel, double *ms, int64_t *launches)
 {
     if (!r || kernel < 0 || kernel >= kKernels || !ms || !launches) return RVEA_EINVAL;
-    HIPCHK(r, hipStreamSynchronize(r->stream));
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     double tot = 0.0;
     int64_t n = 0;
     for (auto &ev : r->events) {
@@ -642,9 +667,12 @@ rvea_status rvea_kernel_time(rvea_run r, int kernel, double *ms, int64_t *launch
     return RVEA_OK;
 }
 
+rvea_status rvea_batch_retire(rvea_batch b, rvea_run r);
+
 rvea_status rvea_destroy(rvea_run r)
 {
     if (!r) return RVEA_EINVAL;
+    if (r->batch) rvea_batch_retire(r->batch, r);
     (void)hipStreamSynchronize(r->stream);
     for (auto &ev : r->events) {
         (void)hipEventDestroy(ev.a);
@@ -659,6 +687,201 @@ rvea_status rvea_destroy(rvea_run r)
     delete r;
     return RVEA_OK;
 }
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+rvea_status bfail(rvea_batch b, hipError_t e, const char *what)
+{
+    std::snprintf(b->err, sizeof b->err, "%s: %s", what, hipGetErrorString(e));
+    return RVEA_EDEVICE;
+}
+
+#define BHIPCHK(b, call)                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return bfail(b, e_, #call);                                    \
+    } while (0)
+
+// span tables of every (phase, class) over the admitted runs, uploaded once
+// per membership change
+rvea_status rebuild_plan(rvea_batch b)
+{
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    const int n = (int)b->runs.size();
+    std::vector<RunView> views(n);
+    for (int i = 0; i < n; ++i) views[i] = b->runs[i]->R;
+    std::vector<Span> spans;
+    b->plan.clear();
+    for (int phase = 0; phase < BP_COUNT; ++phase) {
+        std::vector<int> classes;
+        for (int i = 0; i < n; ++i) {
+            const int c = batch_phase_class(phase, views[i]);
+            if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+        }
+        std::sort(classes.begin(), classes.end());
+        for (int c : classes) {
+            rvea_batch_s::Launch L{phase, c, (int64_t)spans.size(), 0, 0};
+            for (int i = 0; i < n; ++i) {
+                if (batch_phase_class(phase, views[i]) != c) continue;
+                const int64_t nb = batch_phase_blocks(phase, views[i]);
+                if (nb <= 0) continue;
+                spans.push_back(Span{L.blocks, i, (int32_t)batch_phase_nbx(phase, views[i])});
+                L.blocks += nb;
+                ++L.n;
+            }
+            if (L.n > 0) b->plan.push_back(L);
+        }
+    }
+    if (n > 0) {
+        BHIPCHK(b, hipMemcpy(b->d_runs, views.data(), sizeof(RunView) * n, hipMemcpyHostToDevice));
+        BHIPCHK(b, hipMemcpy(b->d_spans, spans.data(), sizeof(Span) * spans.size(),
+                             hipMemcpyHostToDevice));
+    }
+    b->dirty = false;
+    ++b->version;
+    return RVEA_OK;
+}
+
+hipError_t enqueue_batch_generation(rvea_batch b, hipStream_t s)
+{
+    for (const auto &L : b->plan) {
+        hipError_t e = launch_batch(L.phase, L.cls, b->d_runs, b->d_spans + L.span_off, L.n,
+                                    L.blocks, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+rvea_status rvea_batch_footprint(int max_runs, size_t *bytes)
+{
+    if (!bytes || max_runs < 1 || max_runs > (1 << 16)) return RVEA_EINVAL;
+    const size_t a = ((size_t)max_runs * sizeof(RunView) + 255) / 256 * 256;
+    const size_t c = ((size_t)BP_COUNT * max_runs * sizeof(Span) + 255) / 256 * 256;
+    *bytes = a + c;
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_create(int max_runs, void *workspace, size_t workspace_bytes,
+                              void *hip_stream, rvea_batch *out)
+{
+    if (!out) return RVEA_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    rvea_status st = rvea_batch_footprint(max_runs, &need);
+    if (st != RVEA_OK) return st;
+    if (!workspace || ((uintptr_t)workspace & 255u)) return RVEA_EINVAL;
+    if (workspace_bytes < need) return RVEA_ENOMEM;
+    rvea_batch b = new rvea_batch_s();
+    b->max_runs = max_runs;
+    b->stream = (hipStream_t)hip_stream;
+    b->d_runs = (RunView *)workspace;
+    b->d_spans = (Span *)((char *)workspace +
+                          ((size_t)max_runs * sizeof(RunView) + 255) / 256 * 256);
+    *out = b;
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_admit(rvea_batch b, rvea_run r)
+{
+    if (!b || !r) return RVEA_EINVAL;
+    if (r->batch || r->phase != 0 || r->timing) return RVEA_ESTATE;
+    if ((int)b->runs.size() >= b->max_runs) return RVEA_ENOMEM;
+    // the run's pending work (creation, earlier generations) precedes the batch
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    r->batch = b;
+    b->runs.push_back(r);
+    b->dirty = true;
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_retire(rvea_batch b, rvea_run r)
+{
+    if (!b || !r || r->batch != b) return RVEA_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->runs.erase(std::find(b->runs.begin(), b->runs.end(), r));
+    r->batch = nullptr;
+    b->dirty = true;
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_step(rvea_batch b)
+{
+    if (!b) return RVEA_EINVAL;
+    if (b->dirty) {
+        rvea_status st = rebuild_plan(b);
+        if (st != RVEA_OK) return st;
+    }
+    if (b->runs.empty()) return RVEA_OK;
+    const bool stable = b->last_step_version == b->version;
+    b->last_step_version = b->version;
+    if (b->use_graphs && (stable || b->graph_version == b->version)) {
+        if (b->graph_version != b->version) {
+            if (b->gexec) {
+                BHIPCHK(b, hipGraphExecDestroy(b->gexec));
+                BHIPCHK(b, hipGraphDestroy(b->graph));
+                b->gexec = nullptr;
+                b->graph = nullptr;
+            }
+            if (!b->cap_stream)
+                BHIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+            BHIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_batch_generation(b, b->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+            if (e != hipSuccess) return bfail(b, e, "batch capture");
+            if (e2 != hipSuccess) return bfail(b, e2, "hipStreamEndCapture");
+            b->graph = g;
+            BHIPCHK(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+            b->graph_version = b->version;
+        }
+        BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+    } else {
+        BHIPCHK(b, enqueue_batch_generation(b, b->stream));
+    }
+    for (rvea_run r : b->runs) {
+        r->t += 1;
+        r->has_selection = true;
+    }
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_set_graphs(rvea_batch b, int enable)
+{
+    if (!b) return RVEA_EINVAL;
+    b->use_graphs = enable != 0;
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_size(rvea_batch b, int *n)
+{
+    if (!b || !n) return RVEA_EINVAL;
+    *n = (int)b->runs.size();
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_synchronize(rvea_batch b)
+{
+    if (!b) return RVEA_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    return RVEA_OK;
+}
+
+rvea_status rvea_batch_destroy(rvea_batch b)
+{
+    if (!b) return RVEA_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    for (rvea_run r : b->runs) r->batch = nullptr;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return RVEA_OK;
+}
+
+const char *rvea_batch_last_error(rvea_batch b) { return b ? b->err : "no batch"; }
 
 const char *rvea_status_str(rvea_status s)
 {

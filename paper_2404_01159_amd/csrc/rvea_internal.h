@@ -24,4 +24,23 @@ hipError_t launch_rerank(const RunView &R, hipStream_t s);
 hipError_t launch_select_back(const RunView &R, hipStream_t s);
 hipError_t launch_adapt(const RunView &R, hipStream_t s);
 
+// Batched phases: one launch advances one phase of every run listed in the
+// span table (runs of the same template class: segment width for the
+// offspring, objective count for the association phases).
+enum BatchPhase {
+    BP_PREP_COUNT, BP_PREP_WRITE, BP_OFFSPRING, BP_IDEAL, BP_ASSOC, BP_RERANK, BP_SURV,
+    BP_NEWPOP, BP_COMMIT, BP_ADAPT, BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
+};
+int batch_phase_class(int phase, const RunView &R);       // template class of a run
+int64_t batch_phase_blocks(int phase, const RunView &R);  // its block count
+int64_t batch_phase_nbx(int phase, const RunView &R);     // row blocks of 2-D phases
+hipError_t launch_batch(int phase, int cls, const RunView *runs, const Span *spans, int n,
+                        int64_t blocks, hipStream_t s);
+hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span *spans, int n,
+                            int64_t blocks, hipStream_t s);
+hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Span *spans,
+                               int n, int64_t blocks, hipStream_t s);
+hipError_t launch_batch_vectors(int phase, int cls, const RunView *runs, const Span *spans,
+                                int n, int64_t blocks, hipStream_t s);
+
 }  // namespace rvea

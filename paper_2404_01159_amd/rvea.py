@@ -28,6 +28,9 @@ EXPORTS = [
     "rvea_get_counters",
     "rvea_set_timing", "rvea_kernel_time", "rvea_synchronize", "rvea_destroy",
     "rvea_status_str", "rvea_last_error",
+    "rvea_batch_footprint", "rvea_batch_create", "rvea_batch_admit", "rvea_batch_retire",
+    "rvea_batch_step", "rvea_batch_set_graphs", "rvea_batch_size", "rvea_batch_synchronize",
+    "rvea_batch_destroy", "rvea_batch_last_error",
 ]
 
 
@@ -77,6 +80,17 @@ def _load():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    for name, args in {
+        "rvea_batch_footprint": [i32, P], "rvea_batch_create": [i32, P, sz, P, P],
+        "rvea_batch_admit": [P, P], "rvea_batch_retire": [P, P], "rvea_batch_step": [P],
+        "rvea_batch_set_graphs": [P, i32], "rvea_batch_size": [P, P],
+        "rvea_batch_synchronize": [P], "rvea_batch_destroy": [P],
+    }.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.rvea_batch_last_error.argtypes = [P]
+    L.rvea_batch_last_error.restype = C.c_char_p
     L.rvea_status_str.argtypes = [C.c_int]
     L.rvea_status_str.restype = C.c_char_p
     L.rvea_last_error.argtypes = [P]
@@ -247,6 +261,72 @@ class Run:
         if self._h:
             lib.rvea_destroy(self._h)
             self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_footprint(max_runs):
+    b = C.c_size_t(0)
+    st = lib.rvea_batch_footprint(max_runs, C.byref(b))
+    if st != RVEA_OK:
+        raise RveaError(st, "rvea_batch_footprint")
+    return b.value
+
+
+class Batch:
+    """Many runs advanced together, one generation per step()."""
+
+    def __init__(self, max_runs, device="cuda:0", stream=None):
+        dev = torch.device(device)
+        nbytes = batch_footprint(max_runs)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._h = C.c_void_p(0)
+        self.runs = []
+        st = lib.rvea_batch_create(max_runs, C.c_void_p(aligned), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        if st != RVEA_OK:
+            raise RveaError(st, "rvea_batch_create: " + lib.rvea_status_str(st).decode())
+
+    def _chk(self, st, what):
+        if st != RVEA_OK:
+            raise RveaError(st, f"{what}: {lib.rvea_status_str(st).decode()} "
+                                f"{lib.rvea_batch_last_error(self._h).decode()}")
+
+    def admit(self, run):
+        self._chk(lib.rvea_batch_admit(self._h, run._h), "rvea_batch_admit")
+        self.runs.append(run)
+
+    def retire(self, run):
+        self._chk(lib.rvea_batch_retire(self._h, run._h), "rvea_batch_retire")
+        self.runs.remove(run)
+
+    def step(self, n=1):
+        for _ in range(n):
+            self._chk(lib.rvea_batch_step(self._h), "rvea_batch_step")
+
+    def set_graphs(self, on):
+        self._chk(lib.rvea_batch_set_graphs(self._h, 1 if on else 0), "rvea_batch_set_graphs")
+
+    def size(self):
+        n = C.c_int(0)
+        self._chk(lib.rvea_batch_size(self._h, C.byref(n)), "rvea_batch_size")
+        return n.value
+
+    def synchronize(self):
+        self._chk(lib.rvea_batch_synchronize(self._h), "rvea_batch_synchronize")
+
+    def close(self):
+        if self._h:
+            lib.rvea_batch_destroy(self._h)
+            self._h = C.c_void_p(0)
+            self.runs = []
 
     def __del__(self):
         try:
