@@ -61,6 +61,54 @@ def cpu_baseline(cfg, budget_s):
                        f"{el:.1f} s")
 
 
+def serving_legs(a):
+    """Served runs (open loop, Poisson arrivals), the same runs all at once
+    (batched capacity), and the same runs one at a time on the plain path."""
+    import torch
+
+    import paper_2404_01159_amd as P
+    from paper_2404_01159_amd.serve import DeviceBackend, Request, Server, latency_summary
+    from workloads import serving_specs
+
+    specs = serving_specs(a.serve_runs, a.serve_rate, seed=0)
+    reqs = [Request(s["rid"], s["arrival"], s["problem"], s["m"], s["d"], s["N"], s["K"],
+                    s["seed"], s["gens"]) for s in specs]
+    out = {"workload": f"{len(reqs)} runs, Poisson {a.serve_rate}/s, m in {{2,3,5,8}}, "
+                       "d in [30,2000], K=N in [100,10011], 100 generations each"}
+    budget = int(a.serve_budget_gib * (1 << 30))
+    be = DeviceBackend(budget, max_runs=256)
+    srv = Server(be, budget, max_runs=256)
+    res = srv.serve(reqs)
+    out["open_loop"] = dict(latency_summary(res), arena_gib=a.serve_budget_gib,
+                            peak_resident_runs=srv.peak_runs, ticks=srv.ticks)
+    del be, srv
+    # saturated: every request present at t = 0, large arena
+    sat = [Request(r.rid, 0.0, r.problem, r.m, r.d, r.N, r.K, r.seed, r.gens) for r in reqs]
+    total = sum(P.footprint(r.problem, r.m, r.d, r.N, r.K, P.default_params()) for r in sat)
+    be = DeviceBackend(total + (1 << 26), max_runs=256)
+    srv = Server(be, total + (1 << 26), max_runs=256)
+    t0 = time.perf_counter()
+    res = srv.serve(sat)
+    el = time.perf_counter() - t0
+    out["batched_all_at_once"] = dict(runs=len(res), runs_per_s=len(res) / el, seconds=el,
+                                      ticks=srv.ticks, arena_gib=total / (1 << 30))
+    del be, srv
+    torch.cuda.synchronize()
+    # one run at a time, plain single-run path (graph per generation)
+    t0 = time.perf_counter()
+    for r in sat:
+        run = P.Run(r.problem, r.m, r.d, r.N, r.K, seed=r.seed,
+                    params=P.default_params(t_max=100))
+        run.run(r.gens)
+        run.synchronize()
+        run.close()
+    el1 = time.perf_counter() - t0
+    out["one_at_a_time"] = dict(runs=len(sat), runs_per_s=len(sat) / el1, seconds=el1)
+    out["batched_over_one_at_a_time"] = out["batched_all_at_once"]["runs_per_s"] / (
+        len(sat) / el1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +119,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-kernel events (for profiler runs)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the served / batched runs legs")
+    ap.add_argument("--serve-runs", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -154,12 +207,16 @@ def main():
                         avg_launch_us=avg_ms * 1e3, launches=n)
         run.close()
 
+    serving = None
+    if not a.no_serving:
+        serving = serving_legs(a)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(cfg, a.cpu_budget)
 
     out = {
-        "metric": "RVEA generations/s at N=10k,m=3,d=500 vs plain",
+        "metric": "RVEA generations/s at N=10k,m=3,d=500 vs plain; served runs/s + p50/p99 latency",
         "value": gens_per_s,
         "unit": "generations/s",
         "n_gpus": 1,
@@ -178,6 +235,7 @@ def main():
         "kernels_avg_us": {k: v[0] * 1e3 for k, v in per_kernel.items()},
         "counters": counters,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

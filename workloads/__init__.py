@@ -72,3 +72,31 @@ def gamma_like(seed, K, lo=0.02, hi=0.2):
 
 def seeds(n, base=0):
     return [base + i for i in range(n)]
+
+
+# Served workload: independent runs arriving as a Poisson stream.  Each draws
+# its problem (the three stand-ins above, in place of DTLZ1-7), m from
+# {2,3,5,8}, d uniform in [30, 2000] and the lattice divisions H uniformly
+# over the values whose count C(H+m-1, m-1) lies in [100, 10011]; N = K.
+SERVE_H_RANGE = {2: (99, 10010), 3: (13, 140), 5: (5, 19), 8: (3, 8)}
+
+
+def lattice_count(H, m):
+    from math import comb
+
+    return comb(H + m - 1, m - 1)
+
+
+def serving_specs(n=256, rate=20.0, seed=0, gens=100):
+    """List of dicts: rid, arrival (s), problem, m, d, N, K, seed, gens."""
+    r = rng(seed)
+    arrivals = np.cumsum(r.exponential(1.0 / rate, size=n)) if rate > 0 else np.zeros(n)
+    out = []
+    for i in range(n):
+        m = int(r.choice([2, 3, 5, 8]))
+        lo, hi = SERVE_H_RANGE[m]
+        H = int(r.integers(lo, hi + 1))
+        K = lattice_count(H, m)
+        out.append(dict(rid=i, arrival=float(arrivals[i]), problem=int(r.integers(1, 4)), m=m,
+                        d=int(r.integers(30, 2001)), N=K, K=K, seed=1000 + i, gens=gens))
+    return out
