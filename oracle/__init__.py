@@ -28,7 +28,22 @@ class OraParams(C.Structure):
         ("p_m", C.c_double),
         ("lb", C.c_double),
         ("ub", C.c_double),
+        ("lq", C.c_void_p),
     ]
+
+
+class OraLQ(C.Structure):
+    _fields_ = [
+        ("A", C.c_void_p),
+        ("B", C.c_void_p),
+        ("x0", C.c_void_p),
+        ("E", C.c_int32),
+        ("T", C.c_int32),
+        ("sigma", C.c_double),
+    ]
+
+
+POLICY_LQ = 100
 
 
 DEFAULTS = dict(alpha=2.0, fr=0.1, t_max=100, eta_c=20.0, eta_m=20.0, p_c=1.0, p_m=1.0,
@@ -37,11 +52,19 @@ DEFAULTS = dict(alpha=2.0, fr=0.1, t_max=100, eta_c=20.0, eta_m=20.0, p_c=1.0, p
 TAG_INIT, TAG_MATE, TAG_SBX, TAG_SBXPAIR, TAG_MUT = 0, 1, 2, 3, 4
 
 
-def params(**kw):
+def params(lq=None, **kw):
+    """ora_params; ``lq`` = dict(A, B, x0, T, sigma) for the policy problem."""
     d = dict(DEFAULTS)
     d.update(kw)
-    return OraParams(d["alpha"], d["fr"], int(d["t_max"]), 0, d["eta_c"], d["eta_m"],
-                     d["p_c"], d["p_m"], d["lb"], d["ub"])
+    p = OraParams(d["alpha"], d["fr"], int(d["t_max"]), 0, d["eta_c"], d["eta_m"],
+                  d["p_c"], d["p_m"], d["lb"], d["ub"], None)
+    if lq is not None:
+        arrs = [_c(lq[k], np.float32) for k in ("A", "B", "x0")]
+        sysd = OraLQ(_p(arrs[0]), _p(arrs[1]), _p(arrs[2]), arrs[2].shape[0], int(lq["T"]),
+                     float(lq["sigma"]))
+        p.lq = C.cast(C.pointer(sysd), C.c_void_p)
+        p._keep = (arrs, sysd)  # the C side holds raw pointers into these
+    return p
 
 
 def lib():
@@ -64,6 +87,9 @@ def lib():
             "ora_front": (i64, [i32, i32, i32, P, i64]),
             "ora_igd": (f64, [P, i64, P, i64, i32]),
             "ora_init": (None, [u64, i64, i32, f64, f64, P, i64]),
+            "ora_bf16": (f64, [f64]),
+            "ora_policy_evaluate": (i32, [i64, P, i64, i32, i32, P, P, P, P]),
+            "ora_init_gauss_rows": (None, [u64, P, i64, i32, f64, f64, f64, P, P]),
             "ora_init_rows": (None, [u64, P, i64, i32, f64, f64, P]),
             "ora_mate": (i64, [u64, i64, i64, i64, P, P]),
             "ora_sbx_beta": (f64, [f64, f64]),
@@ -189,6 +215,38 @@ def init(seed, N, d, lb=0.0, ub=1.0):
     X = np.zeros((N, d), np.float32)
     lib().ora_init(seed, N, d, lb, ub, _p(X), d)
     return X
+
+
+def bf16(x):
+    return float(lib().ora_bf16(float(x)))
+
+
+POLICY_D = 6728
+
+
+def policy_evaluate(X, E, T, A, B, x0):
+    """Objectives (n x 2) of policy genes X (n x 6728) on the linear system."""
+    X = _c(X, np.float32)
+    A = _c(A, np.float32)
+    B = _c(B, np.float32)
+    x0 = _c(x0, np.float32)
+    assert X.shape[1] == POLICY_D and A.shape == (32, 32) and B.shape == (32, 8)
+    assert x0.shape == (E, 32)
+    F = np.zeros((X.shape[0], 2), np.float64)
+    rc = lib().ora_policy_evaluate(X.shape[0], _p(X), X.shape[1], E, T, _p(A), _p(B), _p(x0),
+                                   _p(F))
+    if rc != 0:
+        raise ValueError("ora_policy_evaluate rejected its arguments")
+    return F
+
+
+def init_gauss_rows(seed, rows, d, sigma=0.1, lb=-1.0, ub=1.0, with_pre=False):
+    """Gaussian initial genes of individuals ``rows`` (len(rows) x d float32)."""
+    rows = _c(rows, np.int64)
+    X = np.zeros((len(rows), d), np.float32)
+    pre = np.zeros((len(rows), d), np.float64) if with_pre else None
+    lib().ora_init_gauss_rows(seed, _p(rows), len(rows), d, sigma, lb, ub, _p(X), _p(pre))
+    return (X, pre) if with_pre else X
 
 
 def init_rows(seed, rows, d, lb=0.0, ub=1.0):
@@ -322,15 +380,20 @@ class State:
         self.gamma = _c(gamma, np.float64).copy()
 
 
-def initial_state(problem, m, d, N, K, seed, lb=0.0, ub=1.0):
+def initial_state(problem, m, d, N, K, seed, lb=0.0, ub=1.0, lq=None):
+    """``lq`` = dict(A, B, x0, T, sigma) for the policy problem."""
     H = lattice_H(K, m)
     if H is None:
         raise ValueError("K is not a Das-Dennis lattice count")
     V0 = unit_vectors(H, m)
     X = np.zeros((K, d), np.float32)
-    X[:N] = init(seed, N, d, lb, ub)
     F = np.full((K, m), np.nan)
-    F[:N] = evaluate(problem, m, X[:N])
+    if problem == POLICY_LQ:
+        X[:N] = init_gauss_rows(seed, np.arange(N), d, lq["sigma"], lb, ub)
+        F[:N] = policy_evaluate(X[:N], lq["x0"].shape[0], lq["T"], lq["A"], lq["B"], lq["x0"])
+    else:
+        X[:N] = init(seed, N, d, lb, ub)
+        F[:N] = evaluate(problem, m, X[:N])
     valid = np.zeros(K, np.uint8)
     valid[:N] = 1
     return State(X, F, valid, V0.copy(), V0, gamma(V0))

@@ -102,6 +102,13 @@ static uint32_t uint_below(uint32_t w, uint32_t n)
     return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
 }
 
+static double clipd(double x, double lb, double ub)
+{
+    if (x < lb) x = lb;
+    if (x > ub) x = ub;
+    return x;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Reference vectors: Das-Dennis lattice (Alg. 2 input V_0, unit vectors)   */
 /* ------------------------------------------------------------------------ */
@@ -312,6 +319,129 @@ double ora_igd(const double *F, int64_t n, const double *Fs, int64_t ns, int m)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Policy-rollout problem (the neuroevolution-shaped workload, m = 2).      */
+/* An individual is the flattened weights of a 32 -> 64 -> 64 -> 8 tanh     */
+/* policy: W1 (64x32, row-major [out][in]), b1 (64), W2 (64x64, no bias),   */
+/* W3 (8x64), b3 (8): d = 6,728.  For each of E rollouts from x0[e], T      */
+/* steps of  h1 = tanh(W1 x + b1), h2 = tanh(W2 h1), u = tanh(W3 h2 + b3),  */
+/* x <- A x + B u;  f1 = sum_t |x_t|^2 (t = 1..T), f2 = sum_t |u_t|^2        */
+/* (t = 0..T-1), each averaged over the rollouts.  Weight matrices and      */
+/* every layer input are rounded to bfloat16 (round to nearest even); the   */
+/* biases, A and B stay as given; sums are binary64.                        */
+/* ------------------------------------------------------------------------ */
+double ora_bf16(double x)
+{
+    /* round to nearest even at 8 significant bits (bfloat16), from binary64 */
+    if (!isfinite(x) || x == 0.0) return x;
+    int e;
+    const double fr = frexp(x, &e);  /* |fr| in [0.5, 1) */
+    const double scaled = ldexp(fr, 8);
+    const double r = nearbyint(scaled); /* default rounding mode: to nearest even */
+    return ldexp(r, e - 8);
+}
+
+/* out = tanh(W in + b): W already rounded, in rounded here */
+static void layer(int nout, int nin, const double *W, const float *b, const double *in,
+                  double *out)
+{
+    double inr[64];
+    for (int k = 0; k < nin; ++k) inr[k] = ora_bf16(in[k]);
+    for (int j = 0; j < nout; ++j) {
+        double s = b ? (double)b[j] : 0.0;
+        for (int k = 0; k < nin; ++k) s += W[j * nin + k] * inr[k];
+        out[j] = tanh(s);
+    }
+}
+
+int ora_policy_evaluate(int64_t n, const float *X, int64_t ldx, int E, int T, const float *A,
+                        const float *B, const float *x0, double *F)
+{
+    if (E < 1 || T < 1) return ORA_EINVAL;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *w = X + i * ldx;
+        /* weight matrices in bfloat16; biases b1 (at 2048) and b3 (at 6720) as given */
+        double W1[64 * 32], W2[64 * 64], W3[8 * 64];
+        for (int k = 0; k < 64 * 32; ++k) W1[k] = ora_bf16((double)w[k]);
+        for (int k = 0; k < 64 * 64; ++k) W2[k] = ora_bf16((double)w[2112 + k]);
+        for (int k = 0; k < 8 * 64; ++k) W3[k] = ora_bf16((double)w[6208 + k]);
+        const float *b1 = w + 2048, *b3 = w + 6720;
+        double f1 = 0.0, f2 = 0.0;
+        for (int e = 0; e < E; ++e) {
+            double x[32], h1[64], h2[64], u[8], xn[32];
+            for (int k = 0; k < 32; ++k) x[k] = (double)x0[e * 32 + k];
+            for (int t = 0; t < T; ++t) {
+                layer(64, 32, W1, b1, x, h1);
+                layer(64, 64, W2, NULL, h1, h2);
+                layer(8, 64, W3, b3, h2, u);
+                for (int q = 0; q < 8; ++q) f2 += u[q] * u[q];
+                for (int r = 0; r < 32; ++r) {
+                    double s = 0.0;
+                    for (int k = 0; k < 32; ++k) s += (double)A[r * 32 + k] * x[k];
+                    for (int q = 0; q < 8; ++q) s += (double)B[r * 8 + q] * u[q];
+                    xn[r] = s;
+                }
+                for (int r = 0; r < 32; ++r) {
+                    x[r] = xn[r];
+                    f1 += x[r] * x[r];
+                }
+            }
+        }
+        F[i * 2 + 0] = f1 / (double)E;
+        F[i * 2 + 1] = f2 / (double)E;
+    }
+    return ORA_OK;
+}
+
+/* Gaussian initialization N(0, sigma) clipped to [lb, ub]: the four words of
+ * counter (q, i, 0, TAG_INIT) give two Box-Muller pairs for genes 4q..4q+3:
+ * u1 = (top 24 bits + 1)/2^24 in (0,1], u2 = top 24 bits / 2^24,
+ * (r cos 2 pi u2, r sin 2 pi u2) with r = sqrt(-2 log u1). */
+static void init_row_gauss(uint64_t seed, int64_t i, int d, double sigma, double lb, double ub,
+                           float *x, double *pre)
+{
+    for (int q = 0; 4 * q < d; ++q) {
+        uint32_t w[4];
+        draw(seed, (uint32_t)q, (uint32_t)i, 0u, ORA_TAG_INIT, w);
+        double z[4];
+        for (int h = 0; h < 2; ++h) {
+            const double u1 = (double)((w[2 * h] >> 8) + 1u) * 0x1p-24;
+            const double u2 = (double)(w[2 * h + 1] >> 8) * 0x1p-24;
+            const double r = sqrt(-2.0 * log(u1));
+            const double a = 2.0 * M_PI * u2;
+            z[2 * h] = r * cos(a);
+            z[2 * h + 1] = r * sin(a);
+        }
+        for (int k = 0; k < 4 && 4 * q + k < d; ++k) {
+            const double v = clipd(sigma * z[k], lb, ub);
+            x[4 * q + k] = (float)v;
+            if (pre) pre[4 * q + k] = v;
+        }
+    }
+}
+
+/* rows: individual index of each output row (NULL = 0..n-1); pre (nullable)
+ * receives the binary64 values before rounding */
+void ora_init_gauss_rows(uint64_t seed, const int64_t *rows, int64_t n, int d, double sigma,
+                         double lb, double ub, float *X, double *pre)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q)
+        init_row_gauss(seed, rows ? rows[q] : q, d, sigma, lb, ub, X + q * (int64_t)d,
+                       pre ? pre + q * (int64_t)d : NULL);
+}
+
+/* objectives of n rows of any supported problem */
+static int evaluate_any(const ora_params *P, int problem, int m, int d, int64_t n,
+                        const float *X, int64_t ldx, double *F)
+{
+    if (problem != ORA_POLICY_LQ) return ora_evaluate(problem, m, d, n, X, ldx, F);
+    const ora_lq *q = P->lq;
+    if (!q || m != 2 || d != ORA_POLICY_D) return ORA_EINVAL;
+    return ora_policy_evaluate(n, X, ldx, q->E, q->T, q->A, q->B, q->x0, F);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Initialization (Alg. 2): n randomized individuals.                       */
 /* Reading: uniform in [lb, ub]; slots 0..N-1 valid, N..K-1 empty.          */
 /* gene g of slot i: Philox counter (g/4, i, 0, TAG_INIT), word g%4.        */
@@ -401,12 +531,6 @@ double ora_sbx_beta(double mc, double eta)
     return pow(2.0 - 2.0 * mc, -e);
 }
 
-static double clipd(double x, double lb, double ub)
-{
-    if (x < lb) x = lb;
-    if (x > ub) x = ub;
-    return x;
-}
 
 double ora_pm_delta(double x, double lb, double ub, double mm, double xi)
 {
@@ -742,7 +866,7 @@ int ora_generation(const ora_params *P, int problem, int m, int d, int64_t N, in
     rc = ora_reproduce(P, seed, t, K, N, d, X, d, parents, Xoff, d, NULL);
     if (rc != ORA_OK) goto out;
     memcpy(Fm, F, sizeof(double) * (size_t)(K * m));
-    rc = ora_evaluate(problem, m, d, N, Xoff, d, Fm + K * m);
+    rc = evaluate_any(P, problem, m, d, N, Xoff, d, Fm + K * m);
     if (rc != ORA_OK) goto out;
     for (int64_t i = 0; i < K; ++i) mvalid[i] = valid[i];
     for (int64_t i = K; i < M; ++i) mvalid[i] = 1;
@@ -810,10 +934,15 @@ int ora_run(const ora_params *P, int problem, int m, int d, int64_t N, int64_t K
     memcpy(V, V0, sizeof(double) * (size_t)(K * m));
     ora_gamma(K, m, V, gamma);
     memset(X, 0, sizeof(float) * (size_t)(K * d));
-    ora_init(seed, N, d, P->lb, P->ub, X, d);
+    if (problem == ORA_POLICY_LQ) {
+        if (!P->lq) return ORA_EINVAL;
+        ora_init_gauss_rows(seed, NULL, N, d, P->lq->sigma, P->lb, P->ub, X, NULL);
+    } else {
+        ora_init(seed, N, d, P->lb, P->ub, X, d);
+    }
     for (int64_t j = 0; j < K; ++j) valid[j] = (uint8_t)(j < N);
     for (int64_t j = 0; j < K * m; ++j) F[j] = NAN;
-    int rc = ora_evaluate(problem, m, d, N, X, d, F);
+    int rc = evaluate_any(P, problem, m, d, N, X, d, F);
     if (rc != ORA_OK) return rc;
     for (int64_t t = 1; t <= gens; ++t) {
         rc = ora_generation(P, problem, m, d, N, K, seed, t, X, F, valid, V, V0, gamma, NULL,

@@ -23,6 +23,17 @@ extern "C" {
 #define ORA_TAG_SBXPAIR 3u
 #define ORA_TAG_MUT 4u
 
+/* Linear system of the policy-rollout problem (problem id ORA_POLICY_LQ):
+ * A 32x32 and B 32x8 row-major, x0 E x 32 rollout start states, T steps,
+ * initial genes N(0, sigma) clipped to the bounds. */
+#define ORA_POLICY_LQ 100
+#define ORA_POLICY_D 6728
+typedef struct ora_lq {
+    const float *A, *B, *x0;
+    int32_t E, T;
+    double sigma;
+} ora_lq;
+
 typedef struct ora_params {
     double alpha;  /* APD penalty rate (Eq. 4) */
     double fr;     /* reference-vector adaptation frequency */
@@ -33,8 +44,14 @@ typedef struct ora_params {
     double p_c;   /* crossover probability */
     double p_m;   /* mutation probability; per-site rate is p_m / d */
     double lb, ub;
+    const ora_lq *lq; /* policy-rollout problem only, else NULL */
 } ora_params;
 
+double ora_bf16(double x);
+int ora_policy_evaluate(int64_t n, const float *X, int64_t ldx, int E, int T, const float *A,
+                        const float *B, const float *x0, double *F);
+void ora_init_gauss_rows(uint64_t seed, const int64_t *rows, int64_t n, int d, double sigma,
+                         double lb, double ub, float *X, double *pre);
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 int64_t ora_binomial(int64_t n, int64_t k);
 int64_t ora_lattice_count(int H, int m);

@@ -32,6 +32,14 @@ CONFIGS = {
                                  K=100128, gens=50, seed=0),
 }
 
+# Neuroevolution-shaped workload: N = 4,096 policies (32 -> 64 -> 64 -> 8 tanh,
+# d = 6,728 weights, second hidden layer without bias), m = 2, K = N (H = 4,095),
+# E = 16 rollouts of T = 200 steps on the linear system of ``lq_system``.
+POLICY_LQ = 100
+POLICY_D = 6728
+POLICY_CONFIG = dict(problem=POLICY_LQ, m=2, d=POLICY_D, H=4095, N=4096, K=4096, gens=50,
+                     seed=0, E=16, T=200, sigma=0.1, lb=-1.0, ub=1.0)
+
 DEFAULT_PARAMS = dict(alpha=2.0, fr=0.1, t_max=100, eta_c=20.0, eta_m=20.0, p_c=1.0,
                       p_m=1.0, lb=0.0, ub=1.0)
 
@@ -68,6 +76,24 @@ def objectives(seed, M, m, radius=(0.5, 2.0), offset=0.0):
 def gamma_like(seed, K, lo=0.02, hi=0.2):
     """Positive per-vector angles, for feeding selection in isolation."""
     return rng(seed).uniform(lo, hi, size=K)
+
+
+def lq_system(seed, E=16, n=32, q=8, rho=0.95):
+    """Stable linear system x' = A x + B u: A = rho G / spectral_radius(G) with
+    G ~ N(0,1)^{n x n} (eigenvalues in binary64), B ~ N(0, 0.1^2)^{n x q},
+    E start states x0 ~ N(0, I).  float32 arrays A (n x n), B (n x q), x0 (E x n)."""
+    r = rng(seed)
+    G = r.standard_normal((n, n))
+    A = rho * G / np.max(np.abs(np.linalg.eigvals(G)))
+    B = 0.1 * r.standard_normal((n, q))
+    x0 = r.standard_normal((E, n))
+    return dict(A=A.astype(np.float32), B=B.astype(np.float32), x0=x0.astype(np.float32))
+
+
+def policy_population(seed, n, sigma=0.1, lb=-1.0, ub=1.0):
+    """n x 6728 float32 policy weights N(0, sigma^2) clipped to [lb, ub]."""
+    r = rng(seed)
+    return np.clip(sigma * r.standard_normal((n, POLICY_D)), lb, ub).astype(np.float32)
 
 
 def seeds(n, base=0):
