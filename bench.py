@@ -24,6 +24,7 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed); 78.6 without packed FP32
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix
 WORKLOAD = "large_m3_d500_n10011"
 
 
@@ -40,6 +41,24 @@ def kernel_work(name, run):
     if name == "rerank":
         return "bytes", (K + N) * (m * 4 + 8 + 4)
     return "bytes", 0
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the PMC runs recorded in
+    profiles/traffic.json, or None when that kernel's sources have changed
+    since (the record keeps their SHA-256)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def cpu_baseline(cfg, budget_s):
@@ -59,6 +78,74 @@ def cpu_baseline(cfg, budget_s):
     return dict(value=n / el, unit="generations/s", cores=O.num_threads(), kind="oracle",
                 sample=f"generations 1..{n} of the same workload from its initial state, "
                        f"{el:.1f} s")
+
+
+def policy_flops(N, E, T):
+    """Algorithmic flops of one rollout launch: the three policy products
+    (64x32, 64x64, 8x64 per rollout step) and the dynamics A x + B u."""
+    per_step = 2 * (64 * 32 + 64 * 64 + 8 * 64) + 2 * (32 * 32 + 32 * 8)
+    return N * E * T * per_step
+
+
+def policy_leg(a):
+    """The neuroevolution-shaped workload: 4,096 policies (d = 6,728), m = 2,
+    K = 4,096, 16 rollouts x 200 steps per individual, 50 generations."""
+    import torch
+
+    import oracle as O
+    import paper_2404_01159_amd as P
+    from workloads import POLICY_CONFIG as C, lq_system
+
+    S = dict(lq_system(C["seed"], E=C["E"]), T=C["T"], sigma=C["sigma"])
+    prm = P.default_params(t_max=C["gens"], lb=C["lb"], ub=C["ub"])
+    mk = lambda seed: P.Run(C["problem"], C["m"], C["d"], C["N"], C["K"], seed=seed,
+                            params=prm, system=S)
+    warm = mk(C["seed"] + 1)
+    warm.run(2)
+    warm.synchronize()
+    warm.close()
+    run = mk(C["seed"])
+    run.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.run(C["gens"])
+    run.synchronize()
+    el = time.perf_counter() - t0
+    counters = run.counters()
+    run.close()
+    out = {"workload": "4,096 policies 32-64-64-8 tanh (d=6,728), m=2, K=4,096, 16 rollouts "
+                       "x 200 steps, 50 generations",
+           "generations_per_s": C["gens"] / el, "ms_per_generation": el * 1e3 / C["gens"],
+           "counters": counters}
+    names = ["offspring", "assoc", "rerank", "adapt", "rollout"]
+    run = mk(C["seed"])
+    run.set_timing(range(5))
+    run.run(C["gens"])
+    run.synchronize()
+    per = {}
+    for k in range(5):
+        ms, n = run.kernel_time(k)
+        if n:
+            per[names[k]] = (ms / n, n)
+    run.close()
+    out["kernels_avg_us"] = {k: v[0] * 1e3 for k, v in per.items()}
+    avg_ms, n = per["rollout"]
+    ach = policy_flops(C["N"], C["E"], C["T"]) / (avg_ms * 1e-3) / 1e12
+    out["roofline"] = dict(bound="mfma", achieved=ach, peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
+                           frac=ach / PEAK_BF16_TFLOPS, traffic=None, kernel="rollout",
+                           avg_launch_us=avg_ms * 1e3, launches=n)
+    if not a.no_cpu_baseline:
+        # the oracle's first generation of the same workload (all 4,096 rollouts)
+        op = O.params(lq=S, t_max=C["gens"], lb=C["lb"], ub=C["ub"])
+        st = O.initial_state(C["problem"], C["m"], C["d"], C["N"], C["K"], C["seed"], C["lb"],
+                             C["ub"], lq=S)
+        t0 = time.perf_counter()
+        O.generation(op, C["problem"], C["m"], C["d"], C["N"], C["K"], C["seed"], 1, st)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=1.0 / el, unit="generations/s", cores=O.num_threads(),
+                                   kind="oracle", sample=f"generation 1 of the same workload, "
+                                                         f"{el:.1f} s")
+    return out
 
 
 def serving_legs(a):
@@ -121,6 +208,8 @@ def main():
                     help="skip the per-kernel events (for profiler runs)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the served / batched runs legs")
+    ap.add_argument("--no-policy", action="store_true",
+                    help="skip the policy-rollout (neuroevolution-shaped) workload")
     ap.add_argument("--serve-runs", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
@@ -198,8 +287,10 @@ def main():
         if unit == "bytes":
             ach = work / (avg_ms * 1e-3) / 1e9
             roof = dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s",
-                        frac=ach / PEAK_HBM_GBS, traffic=None, kernel=dom,
-                        avg_launch_us=avg_ms * 1e3, launches=n)
+                        frac=ach / PEAK_HBM_GBS,
+                        traffic=measured_traffic(dom) if a.config == WORKLOAD else None,
+                        kernel=dom, avg_launch_us=avg_ms * 1e3, launches=n,
+                        algorithmic_bytes=work)
         else:
             ach = work / (avg_ms * 1e-3) / 1e12
             roof = dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
@@ -210,6 +301,10 @@ def main():
     serving = None
     if not a.no_serving:
         serving = serving_legs(a)
+
+    policy = None
+    if not a.no_policy:
+        policy = policy_leg(a)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -236,6 +331,7 @@ def main():
         "counters": counters,
         "cpu_baseline": cpu,
         "serving": serving,
+        "policy": policy,
     }
     print(json.dumps(out), flush=True)
 

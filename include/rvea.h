@@ -63,7 +63,8 @@ typedef enum rvea_status {
 typedef enum rvea_problem {
     RVEA_LINEAR_MULTIMODAL = 1,
     RVEA_SPHERE_UNIMODAL = 2,
-    RVEA_SPHERE_MULTIMODAL = 3
+    RVEA_SPHERE_MULTIMODAL = 3,
+    RVEA_POLICY_LQ = 100 /* policy rollouts, m = 2, d = 6728; see rvea_create_policy */
 } rvea_problem;
 
 /* Algorithm parameters (defaults from rvea_default_params in brackets). */
@@ -90,7 +91,8 @@ rvea_status rvea_default_params(rvea_params *out);
 rvea_status rvea_lattice_divisions(int m, int64_t K, int *H);
 
 /* Device bytes a run of this shape needs (workspace size for rvea_create).
- * m in [2,8], d >= m, 1 <= N <= K, K a lattice count for m. */
+ * m in [2,8], d >= m, 1 <= N <= K, K a lattice count for m
+ * (RVEA_POLICY_LQ: m = 2, d = 6728). */
 rvea_status rvea_footprint(int problem, int m, int d, int64_t N, int64_t K,
                            const rvea_params *params, size_t *bytes);
 
@@ -104,6 +106,38 @@ rvea_status rvea_footprint(int problem, int m, int d, int64_t N, int64_t K,
 rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
                         const rvea_params *params, void *workspace, size_t workspace_bytes,
                         void *hip_stream, rvea_run *out);
+
+/* Policy-rollout problem (the neuroevolution setting of Sec. 4.3: objectives
+ * of a policy network obtained by simulation; here a synthetic linear system
+ * stands in for the physics engine).  An individual is the d = 6728 weights
+ * of a 32 -> 64 -> 64 -> 8 tanh network, row-major [out][in]:
+ *   W1 64x32 at 0, b1 64 at 2048, W2 64x64 at 2112, W3 8x64 at 6208, b3 8 at 6720
+ * (the second hidden layer has no bias).  From each of E start states x0[e]
+ * it runs T steps of  u = tanh(W3 tanh(W2 tanh(W1 x + b1)) + b3),
+ * x <- A x + B u;  f1 = sum |x_t|^2 over t = 1..T and f2 = sum |u_t|^2 over
+ * t = 0..T-1, each averaged over the E rollouts, both minimised.  Weight
+ * matrices and layer inputs are rounded to bfloat16 and multiplied on the
+ * matrix cores with binary32 accumulation; biases and the state are
+ * binary32, and A x + B u is accumulated in binary32 from products of the
+ * operands' bfloat16 high and low parts (hi*hi + lo*hi + hi*lo, about 2^-17
+ * relative).  Initial genes are N(0, init_sigma^2) clipped to [lb, ub].
+ * All pointers are host memory, read during rvea_create_policy. */
+typedef struct rvea_lq_system {
+    const float *A;    /* 32 x 32, row-major */
+    const float *B;    /* 32 x 8, row-major */
+    const float *x0;   /* E x 32 start states */
+    int32_t E;         /* rollouts per individual; must be 16 */
+    int32_t T;         /* steps per rollout, >= 1 */
+    double init_sigma; /* standard deviation of the initial genes, > 0 */
+} rvea_lq_system;
+
+/* rvea_create for RVEA_POLICY_LQ (m = 2, d = 6728; the footprint is
+ * rvea_footprint(RVEA_POLICY_LQ, 2, 6728, N, K, ...)).  rvea_create rejects
+ * that problem id, and a policy run cannot join a batch (RVEA_EUNSUPPORTED).
+ * The library keeps its own copy of the system. */
+rvea_status rvea_create_policy(int64_t N, int64_t K, uint64_t seed, const rvea_params *params,
+                               const rvea_lq_system *system, void *workspace,
+                               size_t workspace_bytes, void *hip_stream, rvea_run *out);
 
 /* Alg. 2 line 5 and Appendix B for generation t = completed + 1: draws the
  * N offspring by random mating, SBX and polynomial mutation from the
@@ -175,7 +209,8 @@ rvea_status rvea_get_counters(rvea_run run, rvea_counters *out);
 
 /* Per-kernel timing with HIP events recorded on the run's stream around the
  * selected kernels.  Kernel ids: 0 reproduce+evaluate, 1 association,
- * 2 re-rank+APD, 3 adaptation (vectors + gamma); kernel_mask bit k enables
+ * 2 re-rank+APD, 3 adaptation (vectors + gamma), 4 policy rollouts
+ * (RVEA_POLICY_LQ; id 0 then covers reproduction only); kernel_mask bit k enables
  * id k, 0 disables timing.  rvea_kernel_time returns the summed
  * milliseconds and launch count since timing was last set (waits for the
  * stream). */

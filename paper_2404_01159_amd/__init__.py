@@ -1,7 +1,9 @@
 """MI355X-native TensorRVEA generation: HIP kernels behind a C ABI
 (include/rvea.h, librvea.so) and a thin ctypes binding."""
 from .rvea import (Run, Batch, batch_footprint, Params, default_params, footprint, lattice_divisions, RveaError,
-                   LINEAR_MULTIMODAL, SPHERE_UNIMODAL, SPHERE_MULTIMODAL, EXPORTS, LIB_PATH)
+                   LINEAR_MULTIMODAL, SPHERE_UNIMODAL, SPHERE_MULTIMODAL, POLICY_LQ, POLICY_D, POLICY_E,
+                   EXPORTS, LIB_PATH)
 
 __all__ = ["Run", "Batch", "batch_footprint", "Params", "default_params", "footprint", "lattice_divisions", "RveaError",
-           "LINEAR_MULTIMODAL", "SPHERE_UNIMODAL", "SPHERE_MULTIMODAL", "EXPORTS", "LIB_PATH"]
+           "LINEAR_MULTIMODAL", "SPHERE_UNIMODAL", "SPHERE_MULTIMODAL", "POLICY_LQ", "POLICY_D", "POLICY_E",
+           "EXPORTS", "LIB_PATH"]

@@ -412,6 +412,8 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     const int nroot = (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
     const double nm1 = R.eta_m + 1.0;
     const int nroot_m = (nm1 >= 1.0 && nm1 <= 64.0 && nm1 == (double)(int)nm1) ? (int)nm1 : 0;
+    // the policy problem is evaluated by its own rollout kernel afterwards
+    const bool evaluate = R.problem != kPolicy;
     double g1 = 0.0, g2 = 0.0;
     float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
 
@@ -443,7 +445,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                     c2 = dclip(c2 + pm_delta(c2, lb, ub, sh_mags[seg][1][s_], R.eta_m, nroot_m), lb, ub);
             y1[k] = (float)c1;
             y2[k] = (float)c2;
-            if (g < R.d && g >= R.m - 1) {
+            if (evaluate && g < R.d && g >= R.m - 1) {
                 g1 += (double)dist_term(R.problem, y1[k]);
                 g2 += (double)dist_term(R.problem, y2[k]);
             }
@@ -466,7 +468,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         pos1[k] = __shfl(pv1[k & 3], k >> 2, S);
         pos2[k] = __shfl(pv2[k & 3], k >> 2, S);
     }
-    if (lane == 0) {
+    if (lane == 0 && evaluate) {
         float f[kMaxM];
         finish_objectives(R.problem, R.m, R.d, pos1, g1, f);
         float *F1 = R.Fm + (R.K + o1) * R.m;
@@ -553,10 +555,20 @@ hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span 
 hipError_t launch_init(const RunView &R, hipStream_t s)
 {
     const int S = pick_segment(R.d);
-    if (R.N > 0) RVEA_SEG_DISPATCH(S, k_init, R.N, s, R);
+    if (R.problem == kPolicy) {
+        const hipError_t e = launch_init_gauss(R, s);
+        if (e != hipSuccess) return e;
+    } else if (R.N > 0) {
+        RVEA_SEG_DISPATCH(S, k_init, R.N, s, R);
+    }
     const int64_t empty = R.K - R.N;
     const unsigned g = (unsigned)((empty > 0 ? empty : 1) + 255) / 256;
     k_init_empty<<<g, 256, 0, s>>>(R);
+    if (R.problem == kPolicy) {  // objectives of the initial slots by rollouts
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_rollout(R, s, false);
+    }
     return hipGetLastError();
 }
 

@@ -184,20 +184,25 @@ __device__ __forceinline__ double dotd(const double *a, const double *b)
     return s;
 }
 
-// Re-rank: one 64-lane wave per 16 rows, in three phases.
+// Re-rank: one 64-lane wave per 16 rows, in five phases.
 //   1. four lanes per row split the row's vector chunks: maximum of the chunk
 //      maxima (threshold gmax - 2 eps), then the tiles of the chunks above
 //      the threshold become work items (row, first vector of the tile);
 //   2. the wave walks the flattened (item, vector) space, one vector per
 //      lane: binary64 cosine f.v / (|f| |v|) as an fma chain, then the best
 //      value of each item with the lowest index over its 32 lanes;
-//   3. one lane per row: the best of its items, then angle, APD and the
-//      per-vector atomic minimum (selection), or gamma (GAMMA: rows are the
-//      vectors, i != j, exactly parallel vectors skipped).
-// A row with more than kItems candidate tiles, or left without a usable
-// candidate, is scanned in full in phase 3 (counted).
-constexpr int kItems = 8;
-constexpr int kRows = 16;  // rows per wave
+//   3. one lane per row: the best of its items;
+//   4. a row with more than kItems candidate tiles (crowded vectors that
+//      binary32 cannot separate), beyond the wave's kWaveItems, or left
+//      without a usable candidate is scanned in full by the whole wave
+//      (counted);
+//   5. one lane per row: angle, APD and the per-vector atomic minimum
+//      (selection), or gamma (GAMMA: rows are the vectors, i != j, exactly
+//      parallel vectors skipped).
+constexpr int kItems = 64;       // candidate tiles per row
+constexpr int kWaveItems = 192;  // candidate tiles per wave (16 rows)
+constexpr int kCache = 4;        // candidate chunks per lane kept in registers
+constexpr int kRows = 16;        // rows per wave
 
 template <int MD, bool GAMMA>
 __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int gate)
@@ -207,9 +212,10 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     __shared__ double s_nrm[kRows];
     __shared__ int s_state[kRows];  // 0 inactive, 1 items, 2 zero row, 3 full scan
     __shared__ int s_cnt[kRows], s_off[kRows];
-    __shared__ int s_row[kRows * kItems], s_j0[kRows * kItems];
-    __shared__ double s_best[kRows * kItems];
-    __shared__ int s_bj[kRows * kItems], s_dup[kRows * kItems];
+    __shared__ int s_item[kWaveItems];  // row << 27 | first vector of the tile
+    __shared__ double s_best[kWaveItems];
+    __shared__ int s_bj[kWaveItems];
+    __shared__ unsigned char s_dup[kWaveItems];
 
     const int t = threadIdx.x;
     const int r = t >> 2, sub = t & 3;
@@ -261,15 +267,15 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     // the four lanes of a row are adjacent: combine over xor 1, 2
     thr = fmaxf(thr, __shfl_xor(thr, 1, 64));
     thr = fmaxf(thr, __shfl_xor(thr, 2, 64));
-    // candidate tiles of this lane's chunks (at most kItems kept per lane)
-    int mine = 0, mc[kItems];
-    uint32_t mm[kItems];
+    // candidate tiles of this lane's chunks (the first kCache chunks kept)
+    int mine = 0, mc[kCache];
+    uint32_t mm[kCache];
     if (act && state == 1) {
 #pragma unroll 4
         for (int c = sub; c < R.KC; c += 4) {
             if (R.pmax[(int64_t)c * R.M + i] >= thr) {
                 const uint32_t mk = R.pmask[(int64_t)c * R.M + i];
-                if (mine < kItems) {
+                if (mine < kCache) {
                     mc[mine] = c;
                     mm[mine] = mk;
                 }
@@ -281,10 +287,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     int tot = cnt;
     tot += __shfl_xor(tot, 1, 64);
     tot += __shfl_xor(tot, 2, 64);
-    int more = mine > kItems ? 1 : 0;
-    more |= __shfl_xor(more, 1, 64);
-    more |= __shfl_xor(more, 2, 64);
-    if (act && state == 1 && (tot < 1 || tot > kItems || more)) state = 3;
+    if (act && state == 1 && (tot < 1 || tot > kItems)) state = 3;
     // exclusive prefix of the tile counts over the row's four lanes
     int pre = cnt;
     {
@@ -299,29 +302,33 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         s_cnt[r] = (act && state == 1) ? tot : 0;
     }
     __syncthreads();
-    if (t < kRows) {  // rows' item offsets
-        const int v = s_cnt[t];
-        int incl = v;
-#pragma unroll
-        for (int o = 1; o < kRows; o <<= 1) {
-            const int y = __shfl_up(incl, o, 64);
-            if (t >= o) incl += y;
+    if (t == 0) {  // rows' item offsets, in row order; a row beyond the wave's capacity scans in full
+        int used = 0;
+        for (int q = 0; q < kRows; ++q) {
+            if (s_cnt[q] > 0 && used + s_cnt[q] > kWaveItems) {
+                s_state[q] = 3;
+                s_cnt[q] = 0;
+            }
+            s_off[q] = used;
+            used += s_cnt[q];
         }
-        s_off[t] = incl - v;
     }
     __syncthreads();
     const int total = s_off[kRows - 1] + s_cnt[kRows - 1];
-    if (act && state == 1) {
+    if (act && s_state[r] == 1) {
         int q = s_off[r] + pre;
-        for (int u = 0; u < mine && u < kItems; ++u) {
-            uint32_t mk = mm[u];
+        auto put = [&](int c, uint32_t mk) {
             while (mk) {
                 const int tl = __ffs(mk) - 1;
                 mk &= mk - 1;
-                s_row[q] = r;
-                s_j0[q] = (int)((int64_t)mc[u] * R.CS + (int64_t)tl * kTile);
-                ++q;
+                s_item[q++] = (r << 27) | (int)((int64_t)c * R.CS + (int64_t)tl * kTile);
             }
+        };
+        if (mine <= kCache) {
+            for (int u = 0; u < mine; ++u) put(mc[u], mm[u]);
+        } else {  // more chunks than cached: scan them again
+            for (int c = sub; c < R.KC; c += 4)
+                if (R.pmax[(int64_t)c * R.M + i] >= thr) put(c, R.pmask[(int64_t)c * R.M + i]);
         }
     }
     __syncthreads();
@@ -335,8 +342,8 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         int64_t bj = R.K;
         int dup = 0;
         if (item < total) {
-            const int row = s_row[item];
-            const int64_t j = (int64_t)s_j0[item] + (e & 31);
+            const int row = s_item[item] >> 27;
+            const int64_t j = (int64_t)(s_item[item] & ((1 << 27) - 1)) + (e & 31);
             const int64_t irow = base + row;
             if (j < R.K && (!GAMMA || j != irow)) {
                 double f[MD];
@@ -369,7 +376,73 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     }
     __syncthreads();
 
-    // ---- phase 3: one lane per row
+    // ---- phase 3: one lane per row merges its items
+    __shared__ double s_rb[kRows];
+    __shared__ int s_rj[kRows], s_full[kRows];
+    if (t < kRows) {
+        const int st = s_state[t];
+        double best = -INFINITY;
+        int64_t bj = R.K;
+        bool full = st == 3;
+        if (st == 1) {
+            const int o = s_off[t], n = s_cnt[t];
+            for (int q = o; q < o + n; ++q) {
+                if (s_dup[q]) full = true;
+                const double b = s_best[q];
+                const int64_t j = s_bj[q];
+                if (j < R.K && (b > best || (b == best && j < bj))) {
+                    best = b;
+                    bj = j;
+                }
+            }
+            if (bj >= R.K) full = true;
+        }
+        s_full[t] = full ? 1 : 0;
+        s_rb[t] = best;
+        s_rj[t] = (int)bj;
+    }
+    __syncthreads();
+
+    // ---- phase 4: rows left without a usable candidate set are scanned in
+    // full by the whole wave: every vector in binary64, the maximum with the
+    // lowest index (the plain definition), GAMMA skipping i = j and exactly
+    // parallel vectors
+    for (int rr = 0; rr < kRows; ++rr) {
+        if (!s_full[rr]) continue;  // uniform
+        const int64_t row_i = base + rr;
+        double f[MD];
+#pragma unroll
+        for (int k = 0; k < MD; ++k) f[k] = s_f[rr][k];
+        const double nrm = s_nrm[rr];
+        double best = -INFINITY;
+        int64_t bj = R.K;
+        for (int64_t j = t; j < R.K; j += 64) {
+            if (GAMMA && j == row_i) continue;
+            const double cv = dotd<MD>(f, R.V + j * MD) / (nrm * R.vn[j]);
+            if (GAMMA && cv >= 1.0) continue;
+            if (cv > best) {
+                best = cv;
+                bj = j;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int64_t oj = __shfl_xor(bj, o, 64);
+            if (ob > best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if (t == 0) {
+            atomicAdd(&R.counters[1], 1ull);
+            s_rb[rr] = best;
+            s_rj[rr] = (int)bj;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 5: one lane per row writes the result
     if (t >= kRows) return;
     const int64_t row_i = base + t;
     const int st = s_state[t];
@@ -386,44 +459,14 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         atomicMin(&R.key[0], 0ull);
         return;
     }
-    double best = GAMMA ? -2.0 : -INFINITY;
-    int64_t bj = R.K;
-    bool full = st == 3;
-    if (!full) {
-        const int o = s_off[t], n = s_cnt[t];
-        for (int q = o; q < o + n; ++q) {
-            if (s_dup[q]) full = true;
-            const double b = s_best[q];
-            const int64_t j = s_bj[q];
-            if (j < R.K && (b > best || (b == best && j < bj))) {
-                best = b;
-                bj = j;
-            }
-        }
-        if (bj >= R.K) full = true;
-    }
-    double f[MD];
-#pragma unroll
-    for (int k = 0; k < MD; ++k) f[k] = s_f[t][k];
-    const double nrm = s_nrm[t];
-    if (full) {  // the plain definition: every vector, in index order
-        atomicAdd(&R.counters[1], 1ull);
-        best = GAMMA ? -2.0 : -INFINITY;
-        bj = GAMMA ? -1 : 0;
-        for (int64_t j = 0; j < R.K; ++j) {
-            if (GAMMA && j == row_i) continue;
-            const double cv = dotd<MD>(f, R.V + j * MD) / (nrm * R.vn[j]);
-            if (GAMMA && cv >= 1.0) continue;
-            if (cv > best || (GAMMA && bj < 0)) {
-                best = cv;
-                bj = j;
-            }
-        }
-    }
-    if (GAMMA) {
-        R.gamma[row_i] = bj >= 0 ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
+    double best = s_rb[t];
+    int64_t bj = s_rj[t];
+    if (GAMMA) {  // no other vector: the angle to the nearest neighbour is taken as pi/2
+        R.gamma[row_i] = bj < R.K ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
         return;
     }
+    if (bj >= R.K) bj = 0;  // no finite cosine (cannot happen for a finite, nonzero row)
+    const double nrm = s_nrm[t];
     const double cc = best > 1.0 ? 1.0 : (best < -1.0 ? -1.0 : best);
     const double th = acos(cc);
     const double a = (1.0 + *R.pen * th / R.gamma[bj]) * nrm;

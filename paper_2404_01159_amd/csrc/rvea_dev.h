@@ -20,6 +20,9 @@ constexpr int kMaxM = 8;         // objectives supported
 constexpr int kTile = 32;        // reference vectors per association tile
 constexpr int kMaxSites = 32;    // mutation sites held per child
 constexpr int kBlock = 256;      // threads per block for the streaming kernels
+constexpr int kPolicy = 100;     // problem id of the policy-rollout problem
+constexpr int kPolicyD = 6728;   // its gene count (32 -> 64 -> 64 -> 8 policy)
+constexpr int kPolicyE = 16;     // its rollouts per individual
 
 // Everything a kernel needs to find the run's buffers.  Passed by value.
 struct RunView {
@@ -61,6 +64,10 @@ struct RunView {
     unsigned long long *counters;  // 0 non-finite rows, 1 full rescans, 2 site overflow
     int32_t *vchanged;  // 1: adaptation changed V
     double *pen;        // 1: m (t/t_max)^alpha of the current generation
+    // policy-rollout problem only: A (32x32), B (32x8), x0 (E x 32), binary32
+    const float *lq;
+    int lq_E, lq_T;
+    double lq_sigma;    // initial genes N(0, sigma^2)
 };
 
 // One run's share of a batched launch: blocks [start, next start) belong to

@@ -19,7 +19,8 @@ using namespace rvea;
 
 namespace {
 
-constexpr int kKernels = 4;  // timed kernel ids: offspring, assoc, rerank, gamma
+constexpr int kKernels = 5;  // timed kernel ids: offspring, assoc, rerank, gamma, rollout
+constexpr int kLqFloats = 32 * 32 + 32 * 8 + kPolicyE * 32;  // A, B, x0 of the policy problem
 
 struct Layout {
     int ld, stride, KC, CS;
@@ -31,7 +32,7 @@ enum Buf {
     B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_FN, B_ROWN, B_VALIDN, B_MVALID, B_PARENTS, B_VS,
     B_NVALID, B_STAMP, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
     B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_BCOUNT, B_FREECNT, B_PEN,
-    B_COUNT
+    B_LQ, B_COUNT
 };
 
 int64_t binomial(int64_t n, int64_t k)
@@ -58,7 +59,11 @@ int find_H(int m, int64_t K)
 
 rvea_status check_args(int problem, int m, int d, int64_t N, int64_t K, const rvea_params &p)
 {
-    if (problem < 1 || problem > 3) return RVEA_EINVAL;
+    if (problem == kPolicy) {
+        if (m != 2 || d != kPolicyD) return RVEA_EINVAL;
+    } else if (problem < 1 || problem > 3) {
+        return RVEA_EINVAL;
+    }
     if (m < 2 || m > kMaxM || d < m || d > (1 << 26)) return RVEA_EINVAL;
     if (K < 1 || K > (int64_t)1 << 27 || N < 1 || N > K) return RVEA_EINVAL;
     if (find_H(m, K) == 0) return RVEA_EINVAL;
@@ -69,7 +74,7 @@ rvea_status check_args(int problem, int m, int d, int64_t N, int64_t K, const rv
     return RVEA_OK;
 }
 
-void make_layout(int m, int d, int64_t N, int64_t K, Layout &L)
+void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
 {
     const int64_t M = K + N;
     L.ld = (d + 31) / 32 * 32;
@@ -92,7 +97,8 @@ void make_layout(int m, int d, int64_t N, int64_t K, Layout &L)
         (size_t)K * m * 8, (size_t)K * L.stride * 4, (size_t)K * 8, (size_t)K * 8,
         (size_t)m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
         (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4,
-        (size_t)((K + N + 255) / 256) * 4, 4, 8};
+        (size_t)((K + N + 255) / 256) * 4, 4, 8,
+        problem == kPolicy ? (size_t)kLqFloats * 4 : 0};
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -250,14 +256,18 @@ rvea_status rvea_footprint(int problem, int m, int d, int64_t N, int64_t K,
     const rvea_status st = check_args(problem, m, d, N, K, p);
     if (st != RVEA_OK) return st;
     Layout L;
-    make_layout(m, d, N, K, L);
+    make_layout(problem, m, d, N, K, L);
     *bytes = L.total;
     return RVEA_OK;
 }
 
-rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
-                        const rvea_params *params, void *workspace, size_t workspace_bytes,
-                        void *hip_stream, rvea_run *out)
+}  // extern "C"
+
+namespace {
+
+rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
+                       const rvea_params *params, const rvea_lq_system *sys, void *workspace,
+                       size_t workspace_bytes, void *hip_stream, rvea_run *out)
 {
     if (!out) return RVEA_EINVAL;
     *out = nullptr;
@@ -266,8 +276,18 @@ rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_
     rvea_status st = check_args(problem, m, d, N, K, p);
     if (st != RVEA_OK) return st;
     if (!workspace || ((uintptr_t)workspace & 255u)) return RVEA_EINVAL;
+    if (problem == kPolicy) {
+        if (!sys || !sys->A || !sys->B || !sys->x0 || sys->T < 1 || !(sys->init_sigma > 0) ||
+            !std::isfinite(sys->init_sigma))
+            return RVEA_EINVAL;
+        if (sys->E != kPolicyE) {
+            std::snprintf(g_create_err, sizeof g_create_err,
+                          "the policy rollouts run %d start states per individual", kPolicyE);
+            return RVEA_EUNSUPPORTED;
+        }
+    }
     Layout L;
-    make_layout(m, d, N, K, L);
+    make_layout(problem, m, d, N, K, L);
     if (workspace_bytes < L.total) return RVEA_ENOMEM;
 
     rvea_run r = new rvea_run_s();
@@ -341,8 +361,25 @@ rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_
     R.t_done = (int64_t *)(w + L.off[B_TDONE]);
     R.counters = (unsigned long long *)(w + L.off[B_COUNTERS]);
     R.vchanged = (int32_t *)(w + L.off[B_VCHANGED]);
+    hipError_t e = hipSuccess;
+    if (problem == kPolicy) {
+        float *lq = (float *)(w + L.off[B_LQ]);
+        R.lq = lq;
+        R.lq_E = sys->E;
+        R.lq_T = sys->T;
+        R.lq_sigma = sys->init_sigma;
+        e = hipMemcpyAsync(lq, sys->A, 1024 * 4, hipMemcpyHostToDevice, r->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lq + 1024, sys->B, 256 * 4, hipMemcpyHostToDevice, r->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(lq + 1280, sys->x0, (size_t)kPolicyE * 32 * 4,
+                               hipMemcpyHostToDevice, r->stream);
+        // the caller may free the host arrays once this returns
+        if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    }
 
-    hipError_t e = hipMemsetAsync(R.counters, 0, 3 * sizeof(unsigned long long), r->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(R.counters, 0, 3 * sizeof(unsigned long long), r->stream);
     if (e == hipSuccess) e = hipMemsetAsync(R.vchanged, 0, 4, r->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(R.stamp, 0xff, (size_t)(K + N) * 4, r->stream);
@@ -360,6 +397,32 @@ rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_
     return RVEA_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+rvea_status rvea_create(int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
+                        const rvea_params *params, void *workspace, size_t workspace_bytes,
+                        void *hip_stream, rvea_run *out)
+{
+    if (problem == kPolicy) {
+        std::snprintf(g_create_err, sizeof g_create_err,
+                      "the policy problem is created with rvea_create_policy");
+        if (out) *out = nullptr;
+        return RVEA_EINVAL;
+    }
+    return create_run(problem, m, d, N, K, seed, params, nullptr, workspace, workspace_bytes,
+                      hip_stream, out);
+}
+
+rvea_status rvea_create_policy(int64_t N, int64_t K, uint64_t seed, const rvea_params *params,
+                               const rvea_lq_system *system, void *workspace,
+                               size_t workspace_bytes, void *hip_stream, rvea_run *out)
+{
+    return create_run(kPolicy, 2, kPolicyD, N, K, seed, params, system, workspace,
+                      workspace_bytes, hip_stream, out);
+}
+
 rvea_status rvea_step(rvea_run r)
 {
     if (!r) return RVEA_EINVAL;
@@ -367,6 +430,10 @@ rvea_status rvea_step(rvea_run r)
     HIPCHK(r, launch_prepare(r->R, r->stream));
     rvea_status st = timed(r, 0, [&] { return launch_offspring(r->R, r->stream); }, "offspring");
     if (st != RVEA_OK) return st;
+    if (r->R.problem == kPolicy) {
+        st = timed(r, 4, [&] { return launch_rollout(r->R, r->stream, true); }, "rollout");
+        if (st != RVEA_OK) return st;
+    }
     r->phase = 1;
     return RVEA_OK;
 }
@@ -406,6 +473,7 @@ hipError_t enqueue_generation(const RunView &R, hipStream_t s, bool adapt)
 {
     hipError_t e = launch_prepare(R, s);
     if (e == hipSuccess) e = launch_offspring(R, s);
+    if (e == hipSuccess && R.problem == kPolicy) e = launch_rollout(R, s, true);
     if (e == hipSuccess) e = launch_select_front(R, s);
     if (e == hipSuccess) e = launch_assoc(R, s);
     if (e == hipSuccess) e = launch_rerank(R, s);
@@ -788,6 +856,7 @@ rvea_status rvea_batch_admit(rvea_batch b, rvea_run r)
 {
     if (!b || !r) return RVEA_EINVAL;
     if (r->batch || r->phase != 0 || r->timing) return RVEA_ESTATE;
+    if (r->R.problem == kPolicy) return RVEA_EUNSUPPORTED;
     if ((int)b->runs.size() >= b->max_runs) return RVEA_ENOMEM;
     // the run's pending work (creation, earlier generations) precedes the batch
     HIPCHK(r, hipStreamSynchronize(r->stream));

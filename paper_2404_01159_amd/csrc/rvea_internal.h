@@ -23,6 +23,9 @@ hipError_t launch_assoc(const RunView &R, hipStream_t s);
 hipError_t launch_rerank(const RunView &R, hipStream_t s);
 hipError_t launch_select_back(const RunView &R, hipStream_t s);
 hipError_t launch_adapt(const RunView &R, hipStream_t s);
+hipError_t launch_init_gauss(const RunView &R, hipStream_t s);
+// objectives of the N initial slots (offspring = false) or of the offspring
+hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring);
 
 // Batched phases: one launch advances one phase of every run listed in the
 // span table (runs of the same template class: segment width for the

@@ -18,10 +18,12 @@ LIB_PATH = os.path.join(_HERE, "librvea.so")
 
 RVEA_OK, RVEA_EINVAL, RVEA_ENOMEM, RVEA_EDEVICE, RVEA_ESTATE, RVEA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 LINEAR_MULTIMODAL, SPHERE_UNIMODAL, SPHERE_MULTIMODAL = 1, 2, 3
-KERNEL_OFFSPRING, KERNEL_ASSOC, KERNEL_RERANK, KERNEL_GAMMA = 0, 1, 2, 3
+POLICY_LQ, POLICY_M, POLICY_D, POLICY_E = 100, 2, 6728, 16
+KERNEL_OFFSPRING, KERNEL_ASSOC, KERNEL_RERANK, KERNEL_GAMMA, KERNEL_ROLLOUT = 0, 1, 2, 3, 4
 
 EXPORTS = [
     "rvea_default_params", "rvea_lattice_divisions", "rvea_footprint", "rvea_create",
+    "rvea_create_policy",
     "rvea_step", "rvea_select", "rvea_adapt", "rvea_run_generations", "rvea_set_graphs",
     "rvea_get_state",
     "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
@@ -40,6 +42,11 @@ class Params(C.Structure):
         ("reserved", C.c_int32), ("eta_c", C.c_double), ("eta_m", C.c_double),
         ("p_c", C.c_double), ("p_m", C.c_double), ("lb", C.c_double), ("ub", C.c_double),
     ]
+
+
+class LQSystem(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("B", C.c_void_p), ("x0", C.c_void_p), ("E", C.c_int32),
+                ("T", C.c_int32), ("init_sigma", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -63,6 +70,7 @@ def _load():
         "rvea_lattice_divisions": [i32, i64, P],
         "rvea_footprint": [i32, i32, i32, i64, i64, P, P],
         "rvea_create": [i32, i32, i32, i64, i64, u64, P, P, sz, P, P],
+        "rvea_create_policy": [i64, i64, u64, P, P, P, sz, P, P],
         "rvea_step": [P], "rvea_select": [P], "rvea_adapt": [P],
         "rvea_run_generations": [P, i32],
         "rvea_set_graphs": [P, i32],
@@ -136,7 +144,7 @@ class Run:
     """
 
     def __init__(self, problem, m, d, N, K, seed=0, params=None, device="cuda:0",
-                 stream=None, workspace=None):
+                 stream=None, workspace=None, system=None):
         self.problem, self.m, self.d, self.N, self.K = problem, m, d, N, K
         self.M = K + N
         self.seed = seed
@@ -152,9 +160,26 @@ class Run:
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self._h = C.c_void_p(0)
         with torch.cuda.device(dev):
-            st = lib.rvea_create(problem, m, d, N, K, C.c_uint64(seed), C.byref(self.params),
-                                 C.c_void_p(aligned), avail, C.c_void_p(self.stream.cuda_stream),
-                                 C.byref(self._h))
+            if problem == POLICY_LQ:
+                # system: dict(A 32x32, B 32x8, x0 E x 32, T, sigma); None is rejected
+                sysp = None
+                if system is not None:
+                    arrs = [np.ascontiguousarray(system[k], np.float32)
+                            for k in ("A", "B", "x0")]
+                    if arrs[0].shape != (32, 32) or arrs[1].shape != (32, 8) or \
+                            arrs[2].ndim != 2 or arrs[2].shape[1] != 32:
+                        raise ValueError("system: A 32x32, B 32x8, x0 E x 32")
+                    sysd = LQSystem(_p(arrs[0]), _p(arrs[1]), _p(arrs[2]), arrs[2].shape[0],
+                                    int(system["T"]), float(system.get("sigma", 0.1)))
+                    sysp = C.byref(sysd)
+                st = lib.rvea_create_policy(N, K, C.c_uint64(seed), C.byref(self.params),
+                                            sysp, C.c_void_p(aligned), avail,
+                                            C.c_void_p(self.stream.cuda_stream),
+                                            C.byref(self._h))
+            else:
+                st = lib.rvea_create(problem, m, d, N, K, C.c_uint64(seed), C.byref(self.params),
+                                     C.c_void_p(aligned), avail,
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
         if st != RVEA_OK:
             raise RveaError(st, "rvea_create: " + lib.rvea_status_str(st).decode() + ": "
                             + lib.rvea_last_error(None).decode())

@@ -176,6 +176,28 @@ def test_nonfinite_rows_are_dropped(P, O):
     run.close()
 
 
+def test_crowded_vectors(P, O):
+    """Adapted vectors crowded far below binary32 resolution (axis ranges
+    1 : 1e-3, 4,096 vectors, m = 2): gamma of every vector and one full
+    selection still match the oracle; rows whose candidate tiles exceed the
+    re-rank's capacity take the exact full scan."""
+    problem, m, d, N, K = 2, 2, 12, 4096, 4096
+    prm = P.default_params(t_max=50)
+    run = P.Run(problem, m, d, N, K, seed=3, params=prm)
+    st = run.get_state()
+    V = O.unit_vectors(K - 1, m) * np.array([1.0, 1e-3])
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = st["F"].copy()
+    F[:, 0] *= 1e3
+    run.set_state(st["X"], F, st["valid"], V=V, gamma=None, t=3)
+    st2 = run.get_state()
+    assert np.allclose(st2["gamma"], O.gamma(V), rtol=1e-13, atol=0)
+    stats = lockstep(P, O, run, prm, 1, new_stats())
+    assert stats["near_ties"] <= max(1, 1e-4 * stats["vectors"]), stats
+    assert run.counters()["full_rescans"] > 0
+    run.close()
+
+
 def test_headline_size_stages(P, O):
     """Full 10,011-vector, d=500 shape: two generations, the second adapting."""
     problem, m, d, N, K = 1, 3, 500, 10011, 10011

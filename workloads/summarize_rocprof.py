@@ -1,7 +1,11 @@
 """Turn rocprofv3 CSV output into the short text summaries kept in profiles/.
 
 usage: python workloads/summarize_rocprof.py stats <kernel_stats.csv> [title]
+       python workloads/summarize_rocprof.py trace <kernel_trace.csv> [title]
        python workloads/summarize_rocprof.py pmc <counter_collection.csv> [title]
+
+`trace` groups dispatches by kernel and grid size, which separates the
+workloads of one run (their grids differ).
 """
 import collections
 import csv
@@ -18,11 +22,28 @@ def stats(path):
     return "\n".join(out)
 
 
+def trace(path):
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.defaultdict(list)
+    for r in rows:
+        grid = "x".join(r[f"Grid_Size_{a}"] for a in "XYZ")
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        agg[(r["Kernel_Name"][:70], grid, r["Workgroup_Size_X"])].append(dur)
+    tot = sum(sum(v) for v in agg.values())
+    out = ["| kernel | grid (threads) | block | calls | avg us | min us | max us | share |",
+           "|---|---|---|---|---|---|---|---|"]
+    for (k, g, b), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        out.append("| `%s` | %s | %s | %d | %.2f | %.2f | %.2f | %.1f%% |" % (
+            k, g, b, len(v), sum(v) / len(v), min(v), max(v), 100 * sum(v) / tot))
+    return "\n".join(out)
+
+
 def pmc(path):
     rows = list(csv.DictReader(open(path)))
     agg = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in rows:
-        agg[r["Kernel_Name"][:70]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        key = "%s` grid %s `" % (r["Kernel_Name"][:70], r["Grid_Size"])
+        agg[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
     names = sorted({c for v in agg.values() for c in v})
     out = ["| kernel | dispatches | " + " | ".join(f"{c} (avg/dispatch)" for c in names) + " |",
            "|---|---|" + "---|" * len(names)]
@@ -38,4 +59,4 @@ if __name__ == "__main__":
     title = sys.argv[3] if len(sys.argv) > 3 else ""
     if title:
         print(f"## {title}\n")
-    print(stats(path) if mode == "stats" else pmc(path))
+    print({"stats": stats, "trace": trace, "pmc": pmc}[mode](path))
