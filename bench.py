@@ -105,6 +105,7 @@ def policy_leg(a):
     warm.synchronize()
     warm.close()
     run = mk(C["seed"])
+    tuning = run.autotune() if not a.no_autotune else None
     run.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -116,9 +117,11 @@ def policy_leg(a):
     out = {"workload": "4,096 policies 32-64-64-8 tanh (d=6,728), m=2, K=4,096, 16 rollouts "
                        "x 200 steps, 50 generations",
            "generations_per_s": C["gens"] / el, "ms_per_generation": el * 1e3 / C["gens"],
-           "counters": counters}
+           "counters": counters, "assoc_tiles": tuning}
     names = ["offspring", "assoc", "rerank", "adapt", "rollout"]
     run = mk(C["seed"])
+    if not a.no_autotune:
+        run.autotune()
     run.set_timing(range(5))
     run.run(C["gens"])
     run.synchronize()
@@ -208,6 +211,8 @@ def main():
                     help="skip the per-kernel events (for profiler runs)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the served / batched runs legs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default association tiles")
     ap.add_argument("--no-policy", action="store_true",
                     help="skip the policy-rollout (neuroevolution-shaped) workload")
     ap.add_argument("--serve-runs", type=int, default=256)
@@ -250,9 +255,11 @@ def main():
     warm.close()
     del warm
 
-    # timed pass: a fresh run, every generation one HIP-graph launch
+    # timed pass: a fresh run, association tiles autotuned on its first
+    # generation (nothing committed), every generation one HIP-graph launch
     run = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"],
                 params=prm, device="cuda:0")
+    tuning = run.autotune() if not a.no_autotune else None
     run.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -271,6 +278,8 @@ def main():
     if not a.no_timing:
         run = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"],
                     params=prm, device="cuda:0")
+        if not a.no_autotune:
+            run.autotune()
         run.set_timing([0, 1, 2])
         run.run(a.steps)
         run.synchronize()
@@ -328,6 +337,7 @@ def main():
                    "generations_timed": a.steps, "survivors_final": int(st["valid"].sum())},
         "roofline": roof,
         "kernels_avg_us": {k: v[0] * 1e3 for k, v in per_kernel.items()},
+        "assoc_tiles": tuning,
         "counters": counters,
         "cpu_baseline": cpu,
         "serving": serving,

@@ -217,6 +217,28 @@ rvea_status rvea_get_counters(rvea_run run, rvea_counters *out);
 rvea_status rvea_set_timing(rvea_run run, int kernel_mask);
 rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *launches);
 
+/* Association tile autotuner.  The association pass (Alg. 1's angle
+ * computation, Eq. 2) can run with 1, 2 or 4 rows per lane and with vector
+ * chunks of 32..1024 vectors (at least the default length; fewer chunks mean
+ * fewer per-chunk partials to write and re-read).  rvea_autotune draws the
+ * next generation's offspring and ideal point without committing anything,
+ * times every candidate on them with HIP events (best of three launches) and
+ * keeps the fastest for the rest of the run (the adaptation's gamma pass
+ * included).  Results do not depend on the choice: the association is
+ * finished in binary64 over candidate tiles.  Needs the run between
+ * generations, outside a batch and with timing off (RVEA_ESTATE); waits for
+ * the stream; afterwards rvea_get_selection reports RVEA_ESTATE until the
+ * next rvea_select.  out may be NULL. */
+typedef struct rvea_tuning {
+    int32_t rows_per_lane;  /* chosen */
+    int32_t chunk_vectors;  /* chosen */
+    int32_t candidates;     /* configurations timed */
+    int32_t reserved;
+    double assoc_us;        /* best time of the chosen configuration */
+    double default_us;      /* best time of the default one */
+} rvea_tuning;
+rvea_status rvea_autotune(rvea_run run, rvea_tuning *out);
+
 rvea_status rvea_synchronize(rvea_run run);
 rvea_status rvea_destroy(rvea_run run);
 

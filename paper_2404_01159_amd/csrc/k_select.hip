@@ -67,6 +67,36 @@ __device__ __forceinline__ void ideal_body(const RunView &R, int64_t bx)
 // margin used is 16u per side.
 __device__ __forceinline__ float two_eps(float nrm) { return 0x1p-19f * nrm; }
 
+// Gamma pass (rows are the unit vectors themselves): the single-precision
+// score is minus the squared distance |v_i - v_j|^2 = 2 - 2 cos, whose error
+// scales with the distance, so that nearly parallel vectors (far below the
+// resolution of a binary32 cosine near 1) stay separable.  With v rounded to
+// binary32 (2^-24 per component), the per-component differences off by at
+// most 3 * 2^-24 and an fma chain of m <= 8 squares, a score at squared
+// distance S is off by at most 2^-24 (17 sqrt(S) + 8 S) + 2^-42; 2 eps doubles
+// it and adds a factor 2 margin.
+__device__ __forceinline__ float two_eps_dist(float S)
+{
+    return 0x1p-22f * (17.0f * sqrtf(S) + 8.0f * S) + 0x1p-40f;
+}
+
+// -|a - v|^2 over MD components
+template <int MD>
+__device__ __forceinline__ float negdist(const float *a, const float4 *v)
+{
+    const float w[8] = {v[0].x, v[0].y, v[0].z, v[0].w,
+                        MD > 4 ? v[1].x : 0.f, MD > 4 ? v[1].y : 0.f,
+                        MD > 4 ? v[1].z : 0.f, MD > 4 ? v[1].w : 0.f};
+    float t = a[0] - w[0];
+    float s = t * t;
+#pragma unroll
+    for (int k = 1; k < MD; ++k) {
+        t = a[k] - w[k];
+        s = fmaf(t, t, s);
+    }
+    return -s;
+}
+
 template <int MD>
 __device__ __forceinline__ float dotf(const float *f, const float4 *v)
 {
@@ -144,8 +174,8 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
             }
 #pragma unroll
             for (int r = 0; r < RR; ++r) {
-                float sa = dotf<MD>(f[r], va);
-                float sb = dotf<MD>(f[r], vb);
+                float sa = GAMMA ? negdist<MD>(f[r], va) : dotf<MD>(f[r], va);
+                float sb = GAMMA ? negdist<MD>(f[r], vb) : dotf<MD>(f[r], vb);
                 if (GAMMA) {
                     sa = rows[r] == jt + jj ? -INFINITY : sa;
                     sb = rows[r] == jt + jj + 1 ? -INFINITY : sb;
@@ -156,13 +186,13 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
             const uint32_t bit = 1u << tl;
-            if (tm[r] > cm[r] + e2[r]) {
-                cm[r] = tm[r];
-                mk[r] = bit;
-            } else if (tm[r] >= cm[r] - e2[r]) {
-                mk[r] |= bit;
-                cm[r] = fmaxf(cm[r], tm[r]);
-            }
+            // gamma: the margin of the current best squared distance (none
+            // before the first score; it only shrinks as the best improves)
+            const float e = !GAMMA ? e2[r] : (cm[r] == -INFINITY ? 0.f : two_eps_dist(-cm[r]));
+            // branch-free: a new maximum by more than 2 eps restarts the mask
+            const bool up = tm[r] > cm[r] + e, near = tm[r] >= cm[r] - e;
+            mk[r] = up ? bit : (near ? (mk[r] | bit) : mk[r]);
+            cm[r] = near ? fmaxf(cm[r], tm[r]) : cm[r];
         }
     }
 #pragma unroll
@@ -258,15 +288,16 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
             s_nrm[r] = nrm;
         }
         state = (!GAMMA && nrm == 0.0) ? 2 : 1;
-        const float e2 = two_eps(sqrtf(n2f));
         float gm = -INFINITY;
 #pragma unroll 8
         for (int c = sub; c < R.KC; c += 4) gm = fmaxf(gm, R.pmax[(int64_t)c * R.M + i]);
-        thr = gm - e2;
+        thr = gm;
+        if (!GAMMA) thr = gm - two_eps(sqrtf(n2f));
     }
     // the four lanes of a row are adjacent: combine over xor 1, 2
     thr = fmaxf(thr, __shfl_xor(thr, 1, 64));
     thr = fmaxf(thr, __shfl_xor(thr, 2, 64));
+    if (GAMMA && act && thr > -INFINITY) thr -= two_eps_dist(-thr);  // scores are -|v_i - v_j|^2
     // candidate tiles of this lane's chunks (the first kCache chunks kept)
     int mine = 0, mc[kCache];
     uint32_t mm[kCache];
@@ -615,13 +646,30 @@ hipError_t launch_select_front(const RunView &R, hipStream_t s)
     default: CALL(8); break;                                                                 \
     }
 
-hipError_t launch_assoc(const RunView &R, hipStream_t s)
+// association launch with R.rr rows per lane (1, 2 or 4) and R.KC chunks
+template <bool GAMMA>
+static void assoc_launch(const RunView &R, hipStream_t s, int gate)
 {
-    constexpr int RR = 4;
-    const dim3 grid(blocks(R.M, 256 * RR), (unsigned)R.KC);
-#define RVEA_ASSOC(MV) k_assoc<MV, RR, false><<<grid, 256, 0, s>>>(R, 1)
+    const int64_t rows = GAMMA ? R.K : R.M;
+#define RVEA_ASSOC(MV)                                                                       \
+    switch (R.rr) {                                                                          \
+    case 1:                                                                                  \
+        k_assoc<MV, 1, GAMMA><<<dim3(blocks(rows, 256), (unsigned)R.KC), 256, 0, s>>>(R, gate); \
+        break;                                                                               \
+    case 2:                                                                                  \
+        k_assoc<MV, 2, GAMMA><<<dim3(blocks(rows, 512), (unsigned)R.KC), 256, 0, s>>>(R, gate); \
+        break;                                                                               \
+    default:                                                                                 \
+        k_assoc<MV, 4, GAMMA><<<dim3(blocks(rows, 1024), (unsigned)R.KC), 256, 0, s>>>(R, gate); \
+        break;                                                                               \
+    }
     RVEA_M_DISPATCH(R.m, RVEA_ASSOC);
 #undef RVEA_ASSOC
+}
+
+hipError_t launch_assoc(const RunView &R, hipStream_t s)
+{
+    assoc_launch<false>(R, s, 1);
     return hipGetLastError();
 }
 
@@ -636,11 +684,7 @@ hipError_t launch_rerank(const RunView &R, hipStream_t s)
 // gamma of Eq. 5 through the same two passes, rows = vectors
 hipError_t launch_gamma(const RunView &R, hipStream_t s, int force)
 {
-    constexpr int RR = 4;
-    const dim3 grid(blocks(R.K, 256 * RR), (unsigned)R.KC);
-#define RVEA_GA(MV) k_assoc<MV, RR, true><<<grid, 256, 0, s>>>(R, force)
-    RVEA_M_DISPATCH(R.m, RVEA_GA);
-#undef RVEA_GA
+    assoc_launch<true>(R, s, force);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 #define RVEA_GR(MV) k_rerank<MV, true><<<blocks(R.K, kRows), 64, 0, s>>>(R, force)

@@ -32,6 +32,7 @@ struct RunView {
     int t_max, period;
     double alpha, eta_c, eta_m, p_c, p_m, lb, ub;
     int KC, CS;  // association: number of vector chunks and chunk length
+    int rr;      // association: rows per lane (1, 2 or 4)
 
     float *X;           // (K+N) x ld physical gene rows
     int32_t *slot_row;  // K: physical row of each slot

@@ -328,6 +328,7 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.ub = p.ub;
     R.KC = L.KC;
     R.CS = L.CS;
+    R.rr = 4;
     char *w = (char *)workspace;
     R.X = (float *)(w + L.off[B_X]);
     R.slot_row = (int32_t *)(w + L.off[B_SLOT]);
@@ -737,6 +738,96 @@ rvea_status rvea_kernel_time(rvea_run r, int kernel, double *ms, int64_t *launch
 
 rvea_status rvea_batch_retire(rvea_batch b, rvea_run r);
 
+namespace {
+
+void drop_graphs(rvea_run r)
+{
+    for (int v = 0; v < 2; ++v) {
+        if (r->gexec[v]) (void)hipGraphExecDestroy(r->gexec[v]);
+        if (r->graph[v]) (void)hipGraphDestroy(r->graph[v]);
+        r->gexec[v] = nullptr;
+        r->graph[v] = nullptr;
+    }
+}
+
+}  // namespace
+
+rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
+{
+    if (!r) return RVEA_EINVAL;
+    if (r->phase != 0 || r->batch || r->timing) return RVEA_ESTATE;
+    RunView &R = r->R;
+    const int KC0 = r->L.KC, CS0 = r->L.CS;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    unsigned long long saved[3];
+    HIPCHK(r, hipMemcpy(saved, R.counters, sizeof saved, hipMemcpyDeviceToHost));
+    // the next generation's offspring and ideal point give the association
+    // its real input; nothing is committed, so the state is unchanged
+    HIPCHK(r, launch_prepare(R, r->stream));
+    HIPCHK(r, launch_offspring(R, r->stream));
+    if (R.problem == kPolicy) HIPCHK(r, launch_rollout(R, r->stream, true));
+    HIPCHK(r, launch_select_front(R, r->stream));
+    hipEvent_t a = take_event(r), b = take_event(r);
+    if (!a || !b) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
+    struct Cand {
+        int rr, cs;
+        float ms;
+    };
+    std::vector<Cand> cands;
+    for (int rr : {4, 2, 1})
+        for (int cs = CS0; cs <= 32 * kTile; cs *= 2) {
+            cands.push_back({rr, cs, 0.f});
+            if ((int64_t)cs >= R.K) break;
+        }
+    const int saved_rr = R.rr, saved_cs = R.CS, saved_kc = R.KC;
+    double def_ms = -1.0;
+    for (auto &c : cands) {
+        R.rr = c.rr;
+        R.CS = c.cs;
+        R.KC = (int)((R.K + c.cs - 1) / c.cs);
+        if (R.KC > KC0) continue;  // the workspace holds KC0 chunk partials
+        HIPCHK(r, launch_assoc(R, r->stream));  // warm
+        float best = 1e30f;
+        for (int rep_ = 0; rep_ < 3; ++rep_) {
+            HIPCHK(r, hipEventRecord(a, r->stream));
+            HIPCHK(r, launch_assoc(R, r->stream));
+            HIPCHK(r, hipEventRecord(b, r->stream));
+            HIPCHK(r, hipEventSynchronize(b));
+            float ms = 0.f;
+            HIPCHK(r, hipEventElapsedTime(&ms, a, b));
+            best = std::min(best, ms);
+        }
+        c.ms = best;
+        if (c.rr == saved_rr && c.cs == saved_cs) def_ms = best;
+    }
+    r->pool.push_back(a);
+    r->pool.push_back(b);
+    const Cand *win = nullptr;
+    for (auto &c : cands)
+        if (c.ms > 0.f && (!win || c.ms < win->ms)) win = &c;
+    if (win) {
+        R.rr = win->rr;
+        R.CS = win->cs;
+        R.KC = (int)((R.K + win->cs - 1) / win->cs);
+    } else {
+        R.rr = saved_rr;
+        R.CS = saved_cs;
+        R.KC = saved_kc;
+    }
+    HIPCHK(r, hipMemcpy(R.counters, saved, sizeof saved, hipMemcpyHostToDevice));
+    drop_graphs(r);            // captured with the old launch shapes
+    r->has_selection = false;  // the trial overwrote the last selection's buffers
+    if (out) {
+        out->rows_per_lane = R.rr;
+        out->chunk_vectors = R.CS;
+        out->candidates = (int32_t)cands.size();
+        out->reserved = 0;
+        out->assoc_us = win ? 1e3 * win->ms : -1.0;
+        out->default_us = 1e3 * def_ms;
+    }
+    return RVEA_OK;
+}
+
 rvea_status rvea_destroy(rvea_run r)
 {
     if (!r) return RVEA_EINVAL;
@@ -747,10 +838,7 @@ rvea_status rvea_destroy(rvea_run r)
         (void)hipEventDestroy(ev.b);
     }
     for (auto e : r->pool) (void)hipEventDestroy(e);
-    for (int v = 0; v < 2; ++v) {
-        if (r->gexec[v]) (void)hipGraphExecDestroy(r->gexec[v]);
-        if (r->graph[v]) (void)hipGraphDestroy(r->graph[v]);
-    }
+    drop_graphs(r);
     if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
     delete r;
     return RVEA_OK;

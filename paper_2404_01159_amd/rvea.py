@@ -28,7 +28,7 @@ EXPORTS = [
     "rvea_get_state",
     "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
     "rvea_get_counters",
-    "rvea_set_timing", "rvea_kernel_time", "rvea_synchronize", "rvea_destroy",
+    "rvea_set_timing", "rvea_kernel_time", "rvea_autotune", "rvea_synchronize", "rvea_destroy",
     "rvea_status_str", "rvea_last_error",
     "rvea_batch_footprint", "rvea_batch_create", "rvea_batch_admit", "rvea_batch_retire",
     "rvea_batch_step", "rvea_batch_set_graphs", "rvea_batch_size", "rvea_batch_synchronize",
@@ -47,6 +47,12 @@ class Params(C.Structure):
 class LQSystem(C.Structure):
     _fields_ = [("A", C.c_void_p), ("B", C.c_void_p), ("x0", C.c_void_p), ("E", C.c_int32),
                 ("T", C.c_int32), ("init_sigma", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("rows_per_lane", C.c_int32), ("chunk_vectors", C.c_int32),
+                ("candidates", C.c_int32), ("reserved", C.c_int32), ("assoc_us", C.c_double),
+                ("default_us", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -82,6 +88,7 @@ def _load():
         "rvea_get_counters": [P, P],
         "rvea_set_timing": [P, i32],
         "rvea_kernel_time": [P, i32, P, P],
+        "rvea_autotune": [P, P],
         "rvea_synchronize": [P], "rvea_destroy": [P],
     }
     for name, args in sig.items():
@@ -274,6 +281,13 @@ class Run:
         for k in kernels:
             mask |= 1 << int(k)
         self._chk(lib.rvea_set_timing(self._h, mask), "rvea_set_timing")
+
+    def autotune(self):
+        """Time the association tile candidates and keep the fastest (state unchanged)."""
+        t = Tuning()
+        self._chk(lib.rvea_autotune(self._h, C.byref(t)), "rvea_autotune")
+        return dict(rows_per_lane=t.rows_per_lane, chunk_vectors=t.chunk_vectors,
+                    candidates=t.candidates, assoc_us=t.assoc_us, default_us=t.default_us)
 
     def kernel_time(self, kernel):
         ms = C.c_double(0)

@@ -334,6 +334,30 @@ def test_kernel_timing_records_launches(P):
     assert n == 1
 
 
+@pytest.mark.parametrize("shape", [(1, 3, 40, 1200, 1225), (2, 2, 30, 4000, 4096),
+                                   (3, 5, 25, 1001, 1001)])
+def test_autotuned_tiles_give_identical_runs(P, O, shape):
+    """The association tile autotuner changes launch shapes only: a tuned run
+    equals an untuned one bit for bit (adaptations included), and a tuned run
+    still matches the oracle stage by stage."""
+    problem, m, d, N, K = shape
+    prm = P.default_params(t_max=30)
+    a = P.Run(problem, m, d, N, K, seed=4, params=prm)
+    b = P.Run(problem, m, d, N, K, seed=4, params=prm)
+    t = b.autotune()
+    assert t["rows_per_lane"] in (1, 2, 4) and t["chunk_vectors"] % 32 == 0
+    assert t["candidates"] >= 3 and 0 < t["assoc_us"] <= t["default_us"]
+    a.run(12)
+    b.run(12)
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("X", "F", "valid", "V", "gamma", "t"):
+        assert np.array_equal(sa[k], sb[k], equal_nan=True), k
+    stats = lockstep(P, O, b, prm, 3, new_stats())
+    assert stats["near_ties"] <= max(1, 1e-4 * stats["vectors"]), stats
+    b.close()
+    a.close()
+
+
 def test_graph_replays_match_eager(P):
     """Captured-graph generations equal eager ones, replay after replay, with
     eager work and synchronizations between the replays."""
