@@ -220,7 +220,8 @@ rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *laun
 /* Association tile autotuner.  The association pass (Alg. 1's angle
  * computation, Eq. 2) can run with 1, 2 or 4 rows per lane and with vector
  * chunks of 32..1024 vectors (at least the default length; fewer chunks mean
- * fewer per-chunk partials to write and re-read).  rvea_autotune draws the
+ * fewer per-chunk partials to write and re-read), and its binary64 re-rank
+ * with 4, 8 or 16 rows per wavefront.  rvea_autotune draws the
  * next generation's offspring and ideal point without committing anything,
  * times every candidate on them with HIP events (best of three launches) and
  * keeps the fastest for the rest of the run (the adaptation's gamma pass
@@ -230,12 +231,14 @@ rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *laun
  * the stream; afterwards rvea_get_selection reports RVEA_ESTATE until the
  * next rvea_select.  out may be NULL. */
 typedef struct rvea_tuning {
-    int32_t rows_per_lane;  /* chosen */
-    int32_t chunk_vectors;  /* chosen */
-    int32_t candidates;     /* configurations timed */
-    int32_t reserved;
-    double assoc_us;        /* best time of the chosen configuration */
-    double default_us;      /* best time of the default one */
+    int32_t rows_per_lane;      /* association: chosen rows per lane */
+    int32_t chunk_vectors;      /* association: chosen chunk length */
+    int32_t rerank_rows;        /* binary64 re-rank: chosen rows per wavefront (4, 8, 16) */
+    int32_t candidates;         /* configurations timed */
+    double assoc_us;            /* best time of the chosen association configuration */
+    double default_us;          /* best time of the default one */
+    double rerank_us;           /* best time of the chosen re-rank configuration */
+    double rerank_default_us;   /* best time of the default one */
 } rvea_tuning;
 rvea_status rvea_autotune(rvea_run run, rvea_tuning *out);
 

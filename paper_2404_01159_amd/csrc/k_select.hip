@@ -229,14 +229,18 @@ __device__ __forceinline__ double dotd(const double *a, const double *b)
 //   5. one lane per row: angle, APD and the per-vector atomic minimum
 //      (selection), or gamma (GAMMA: rows are the vectors, i != j, exactly
 //      parallel vectors skipped).
-constexpr int kItems = 64;       // candidate tiles per row
-constexpr int kWaveItems = 192;  // candidate tiles per wave (16 rows)
-constexpr int kCache = 4;        // candidate chunks per lane kept in registers
-constexpr int kRows = 16;        // rows per wave
+constexpr int kItems = 64;   // candidate tiles per row
+constexpr int kCache = 4;    // candidate chunks per lane kept in registers
+constexpr int kBatchRows = 8;  // rows per wave of the batched launch
 
-template <int MD, bool GAMMA>
+// kRows rows per wave (4, 8 or 16): fewer rows give more waves to hide the
+// phases' memory latency on small populations, more rows less per-row
+// overhead on large ones.
+template <int MD, bool GAMMA, int kRows>
 __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int gate)
 {
+    constexpr int kLanes = 64 / kRows;  // lanes per row in phase 1
+    constexpr int kWaveItems = 12 * kRows < kItems ? kItems : 12 * kRows;  // tiles per wave
     if (GAMMA && !gate && *R.vchanged == 0) return;  // uniform: vectors unchanged
     __shared__ double s_f[kRows][MD];
     __shared__ double s_nrm[kRows];
@@ -248,7 +252,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     __shared__ unsigned char s_dup[kWaveItems];
 
     const int t = threadIdx.x;
-    const int r = t >> 2, sub = t & 3;
+    const int r = t / kLanes, sub = t % kLanes;
     const int64_t base = bx * kRows;
     const int64_t i = base + r;
     const int64_t nrows = GAMMA ? R.K : R.M;
@@ -290,20 +294,20 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         state = (!GAMMA && nrm == 0.0) ? 2 : 1;
         float gm = -INFINITY;
 #pragma unroll 8
-        for (int c = sub; c < R.KC; c += 4) gm = fmaxf(gm, R.pmax[(int64_t)c * R.M + i]);
+        for (int c = sub; c < R.KC; c += kLanes) gm = fmaxf(gm, R.pmax[(int64_t)c * R.M + i]);
         thr = gm;
         if (!GAMMA) thr = gm - two_eps(sqrtf(n2f));
     }
     // the four lanes of a row are adjacent: combine over xor 1, 2
-    thr = fmaxf(thr, __shfl_xor(thr, 1, 64));
-    thr = fmaxf(thr, __shfl_xor(thr, 2, 64));
+#pragma unroll
+    for (int o = 1; o < kLanes; o <<= 1) thr = fmaxf(thr, __shfl_xor(thr, o, 64));
     if (GAMMA && act && thr > -INFINITY) thr -= two_eps_dist(-thr);  // scores are -|v_i - v_j|^2
     // candidate tiles of this lane's chunks (the first kCache chunks kept)
     int mine = 0, mc[kCache];
     uint32_t mm[kCache];
     if (act && state == 1) {
 #pragma unroll 4
-        for (int c = sub; c < R.KC; c += 4) {
+        for (int c = sub; c < R.KC; c += kLanes) {
             if (R.pmax[(int64_t)c * R.M + i] >= thr) {
                 const uint32_t mk = R.pmask[(int64_t)c * R.M + i];
                 if (mine < kCache) {
@@ -316,18 +320,17 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         }
     }
     int tot = cnt;
-    tot += __shfl_xor(tot, 1, 64);
-    tot += __shfl_xor(tot, 2, 64);
+#pragma unroll
+    for (int o = 1; o < kLanes; o <<= 1) tot += __shfl_xor(tot, o, 64);
     if (act && state == 1 && (tot < 1 || tot > kItems)) state = 3;
     // exclusive prefix of the tile counts over the row's four lanes
-    int pre = cnt;
-    {
-        const int a1 = __shfl_up(pre, 1, 64);
-        const int c1 = sub >= 1 ? a1 : 0;
-        const int a2 = __shfl_up(pre, 2, 64);
-        const int a3 = __shfl_up(pre, 3, 64);
-        pre = c1 + (sub >= 2 ? a2 : 0) + (sub >= 3 ? a3 : 0);
+    int pre = cnt;  // inclusive scan over the row's lanes, then exclusive
+#pragma unroll
+    for (int o = 1; o < kLanes; o <<= 1) {
+        const int y = __shfl_up(pre, o, 64);
+        if (sub >= o) pre += y;
     }
+    pre -= cnt;
     if (sub == 0) {
         s_state[r] = act ? state : 0;
         s_cnt[r] = (act && state == 1) ? tot : 0;
@@ -358,7 +361,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         if (mine <= kCache) {
             for (int u = 0; u < mine; ++u) put(mc[u], mm[u]);
         } else {  // more chunks than cached: scan them again
-            for (int c = sub; c < R.KC; c += 4)
+            for (int c = sub; c < R.KC; c += kLanes)
                 if (R.pmax[(int64_t)c * R.M + i] >= thr) put(c, R.pmask[(int64_t)c * R.M + i]);
         }
     }
@@ -579,10 +582,10 @@ __global__ __launch_bounds__(256) void k_assoc(RunView R, int gate)
 {
     assoc_body<MD, RR, GAMMA>(R, blockIdx.x, blockIdx.y, gate);
 }
-template <int MD, bool GAMMA>
+template <int MD, bool GAMMA, int ROWS>
 __global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
 {
-    rerank_body<MD, GAMMA>(R, blockIdx.x, gate);
+    rerank_body<MD, GAMMA, ROWS>(R, blockIdx.x, gate);
 }
 __global__ __launch_bounds__(256) void k_surv(RunView R) { surv_body(R, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_newpop(RunView R) { newpop_body(R, blockIdx.x); }
@@ -608,7 +611,7 @@ template <int MD, bool GAMMA>
 __global__ __launch_bounds__(64) void kb_rerank(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
-    rerank_body<MD, GAMMA>(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+    rerank_body<MD, GAMMA, kBatchRows>(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
 }
 __global__ __launch_bounds__(256) void kb_surv(const RunView *runs, const Span *sp, int n)
 {
@@ -673,11 +676,24 @@ hipError_t launch_assoc(const RunView &R, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_rerank(const RunView &R, hipStream_t s)
+// re-rank launch with R.rk rows per wave (4, 8 or 16)
+template <bool GAMMA>
+static void rerank_launch(const RunView &R, hipStream_t s, int gate)
 {
-#define RVEA_RERANK(MV) k_rerank<MV, false><<<blocks(R.M, kRows), 64, 0, s>>>(R, 1)
+    const int64_t rows = GAMMA ? R.K : R.M;
+#define RVEA_RERANK(MV)                                                                      \
+    switch (R.rk) {                                                                          \
+    case 4: k_rerank<MV, GAMMA, 4><<<blocks(rows, 4), 64, 0, s>>>(R, gate); break;           \
+    case 8: k_rerank<MV, GAMMA, 8><<<blocks(rows, 8), 64, 0, s>>>(R, gate); break;           \
+    default: k_rerank<MV, GAMMA, 16><<<blocks(rows, 16), 64, 0, s>>>(R, gate); break;        \
+    }
     RVEA_M_DISPATCH(R.m, RVEA_RERANK);
 #undef RVEA_RERANK
+}
+
+hipError_t launch_rerank(const RunView &R, hipStream_t s)
+{
+    rerank_launch<false>(R, s, 1);
     return hipGetLastError();
 }
 
@@ -687,9 +703,7 @@ hipError_t launch_gamma(const RunView &R, hipStream_t s, int force)
     assoc_launch<true>(R, s, force);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define RVEA_GR(MV) k_rerank<MV, true><<<blocks(R.K, kRows), 64, 0, s>>>(R, force)
-    RVEA_M_DISPATCH(R.m, RVEA_GR);
-#undef RVEA_GR
+    rerank_launch<true>(R, s, force);
     return hipGetLastError();
 }
 
@@ -702,6 +716,13 @@ hipError_t launch_select_back(const RunView &R, hipStream_t s)
 }
 
 int assoc_rows_per_block() { return 256 * 4; }
+int rerank_rows_per_wave() { return kBatchRows; }
+
+int default_rerank_rows(int64_t rows)
+{
+    // enough waves to hide latency: about 8 per SIMD of the 1,024 at 16 rows
+    return rows >= 131072 ? 16 : (rows >= 12288 ? 8 : 4);
+}
 
 hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Span *sp, int n,
                                int64_t blocks, hipStream_t s)

@@ -163,8 +163,8 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
     case BP_SURV: return (R.M + 255) / 256;
     case BP_ASSOC:
     case BP_GAMMA_ASSOC: return batch_phase_nbx(phase, R) * R.KC;
-    case BP_RERANK: return (R.M + 15) / 16;
-    case BP_GAMMA_RERANK: return (R.K + 15) / 16;
+    case BP_RERANK: return (R.M + rerank_rows_per_wave() - 1) / rerank_rows_per_wave();
+    case BP_GAMMA_RERANK: return (R.K + rerank_rows_per_wave() - 1) / rerank_rows_per_wave();
     case BP_NEWPOP:
     case BP_COMMIT:
     case BP_ADAPT: return (R.K + 255) / 256;

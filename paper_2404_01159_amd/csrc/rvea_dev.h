@@ -33,6 +33,7 @@ struct RunView {
     double alpha, eta_c, eta_m, p_c, p_m, lb, ub;
     int KC, CS;  // association: number of vector chunks and chunk length
     int rr;      // association: rows per lane (1, 2 or 4)
+    int rk;      // re-rank: rows per wave (4, 8 or 16)
 
     float *X;           // (K+N) x ld physical gene rows
     int32_t *slot_row;  // K: physical row of each slot

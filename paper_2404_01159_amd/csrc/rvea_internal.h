@@ -11,6 +11,8 @@ namespace rvea {
 
 int pick_segment(int d);
 int assoc_rows_per_block();
+int rerank_rows_per_wave();      // batched launch
+int default_rerank_rows(int64_t rows);  // single-run default for this many rows
 
 hipError_t launch_lattice(const RunView &R, hipStream_t s, int H);
 hipError_t launch_vec_aux(const RunView &R, hipStream_t s);

@@ -51,8 +51,9 @@ class LQSystem(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("rows_per_lane", C.c_int32), ("chunk_vectors", C.c_int32),
-                ("candidates", C.c_int32), ("reserved", C.c_int32), ("assoc_us", C.c_double),
-                ("default_us", C.c_double)]
+                ("rerank_rows", C.c_int32), ("candidates", C.c_int32), ("assoc_us", C.c_double),
+                ("default_us", C.c_double), ("rerank_us", C.c_double),
+                ("rerank_default_us", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -287,7 +288,9 @@ class Run:
         t = Tuning()
         self._chk(lib.rvea_autotune(self._h, C.byref(t)), "rvea_autotune")
         return dict(rows_per_lane=t.rows_per_lane, chunk_vectors=t.chunk_vectors,
-                    candidates=t.candidates, assoc_us=t.assoc_us, default_us=t.default_us)
+                    rerank_rows=t.rerank_rows, candidates=t.candidates, assoc_us=t.assoc_us,
+                    default_us=t.default_us, rerank_us=t.rerank_us,
+                    rerank_default_us=t.rerank_default_us)
 
     def kernel_time(self, kernel):
         ms = C.c_double(0)

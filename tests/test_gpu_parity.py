@@ -346,7 +346,8 @@ def test_autotuned_tiles_give_identical_runs(P, O, shape):
     b = P.Run(problem, m, d, N, K, seed=4, params=prm)
     t = b.autotune()
     assert t["rows_per_lane"] in (1, 2, 4) and t["chunk_vectors"] % 32 == 0
-    assert t["candidates"] >= 3 and 0 < t["assoc_us"] <= t["default_us"]
+    assert t["candidates"] >= 6 and 0 < t["assoc_us"] <= t["default_us"]
+    assert t["rerank_rows"] in (4, 8, 16) and 0 < t["rerank_us"] <= t["rerank_default_us"]
     a.run(12)
     b.run(12)
     sa, sb = a.get_state(), b.get_state()
