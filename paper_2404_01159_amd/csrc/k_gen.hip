@@ -60,9 +60,26 @@ __device__ __forceinline__ void prep_count_body(const RunView &R, int64_t bx)
         R.surv[j] = 0x7fffffff;
     }
     if (j < R.m) {
-        R.zbits[j] = 0xffffffffu;  // ideal point: encodes the largest value
         R.rbits[j] = 0xffffffffu;  // survivors' minimum
         R.rbits[R.m + j] = 0u;     // survivors' maximum
+    }
+    // parent slots that take part in the selection (valid, finite F) and
+    // their share of this generation's ideal point
+    __shared__ uint32_t zmin[kMaxM];
+    if (threadIdx.x < kMaxM) zmin[threadIdx.x] = 0xffffffffu;
+    bool take = false;
+    if (j < R.K) {
+        take = R.valid[j] != 0;
+        bool fin = true;
+        for (int k = 0; k < R.m; ++k) fin = fin && isfinite(R.Fm[j * R.m + k]);
+        if (take && !fin) atomicAdd(&R.counters[0], 1ull);
+        take = take && fin;
+        R.mvalid[j] = take ? 1 : 0;
+    }
+    __syncthreads();
+    for (int k = 0; k < R.m; ++k) {
+        const uint32_t e = wave_min(take ? ord_enc(R.Fm[j * R.m + k]) : 0xffffffffu);
+        if ((threadIdx.x & 63) == 0 && e != 0xffffffffu) atomicMin(&zmin[k], e);
     }
     if (j == 0) {  // Eq. 4 penalty factor m (t/t_max)^alpha of this generation
         *R.pen = (double)R.m * pow((double)gen / (double)R.t_max, R.alpha);
@@ -80,6 +97,8 @@ __device__ __forceinline__ void prep_count_body(const RunView &R, int64_t bx)
         R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
         if (bx == 0) *R.freecnt = 0;
     }
+    if (threadIdx.x < R.m && zmin[threadIdx.x] != 0xffffffffu)
+        atomicMin(&zbuf(R, gen)[threadIdx.x], zmin[threadIdx.x]);
 }
 
 __device__ __forceinline__ void prep_write_body(const RunView &R, int64_t bx)
@@ -353,6 +372,8 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     constexpr int SEGS = kBlock / S;
     __shared__ int32_t sh_sites[SEGS][2][kMaxSites];
     __shared__ double sh_mags[SEGS][2][kMaxSites];
+    __shared__ uint32_t szmin[kMaxM];
+    if (threadIdx.x < kMaxM) szmin[threadIdx.x] = 0xffffffffu;
 
     const int seg = threadIdx.x / S, lane = threadIdx.x % S;
     const int64_t P = (R.N + 1) / 2;
@@ -368,6 +389,9 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                 R.Fm[(R.K + o1) * R.m + k] = __int_as_float(0x7fc00000);
                 if (has2) R.Fm[(R.K + o2) * R.m + k] = __int_as_float(0x7fc00000);
             }
+            R.mvalid[R.K + o1] = 0;
+            if (has2) R.mvalid[R.K + o2] = 0;
+            atomicAdd(&R.counters[0], has2 ? 2ull : 1ull);
         }
         return;  // uniform over the grid
     }
@@ -394,90 +418,113 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                           sh_sites[seg][1], sh_mags[seg][1], &n1, &n2);
     }
     __syncthreads();
-    if (!active) return;
-
-    bool nocross = false;
-    if (R.p_c < 1.0) {
-        const W4 w = draw(R, 0u, (uint32_t)p, t, TAG_SBXPAIR);
-        nocross = ((double)w.w[0] * 0x1p-32) > R.p_c;
-    }
-
-    const float *x1row = R.X + (int64_t)R.slot_row[a] * R.ld;
-    const float *x2row = R.X + (int64_t)R.slot_row[b] * R.ld;
-    float *c1row = R.X + (int64_t)R.off_row[o1] * R.ld;
-    float *c2row = has2 ? R.X + (int64_t)R.off_row[o2] * R.ld : nullptr;
-    const int Q = (R.d + 3) / 4;
-    const double lb = R.lb, ub = R.ub;
-    const double np1 = R.eta_c + 1.0;
-    const int nroot = (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
-    const double nm1 = R.eta_m + 1.0;
-    const int nroot_m = (nm1 >= 1.0 && nm1 <= 64.0 && nm1 == (double)(int)nm1) ? (int)nm1 : 0;
     // the policy problem is evaluated by its own rollout kernel afterwards
     const bool evaluate = R.problem != kPolicy;
-    double g1 = 0.0, g2 = 0.0;
-    float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
-
-    for (int q = lane; q < Q; q += S) {
-        const float4 xa = *reinterpret_cast<const float4 *>(x1row + 4 * q);
-        const float4 xb = *reinterpret_cast<const float4 *>(x2row + 4 * q);
-        const float pa[4] = {xa.x, xa.y, xa.z, xa.w};
-        const float pb[4] = {xb.x, xb.y, xb.z, xb.w};
-        const W4 w = draw(R, (uint32_t)q, (uint32_t)p, t, TAG_SBX);
-        const int g0 = 4 * q;
-        float y1[4], y2[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t word = w.w[k];
-            const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
-            double B = sgn * sbx_beta(unif24(word), R.eta_c, nroot);
-            if (((word >> 6) & 1u) || nocross) B = 1.0;
-            const double xa_ = (double)pa[k], xb_ = (double)pb[k];
-            const double up = 1.0 + B, dn = 1.0 - B;
-            double c1 = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
-            double c2 = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
-            // polynomial mutation if this gene is one of the child's sites
-            const int g = g0 + k;
-            for (int s_ = 0; s_ < n1; ++s_)
-                if (sh_sites[seg][0][s_] == g)
-                    c1 = dclip(c1 + pm_delta(c1, lb, ub, sh_mags[seg][0][s_], R.eta_m, nroot_m), lb, ub);
-            for (int s_ = 0; s_ < n2; ++s_)
-                if (sh_sites[seg][1][s_] == g)
-                    c2 = dclip(c2 + pm_delta(c2, lb, ub, sh_mags[seg][1][s_], R.eta_m, nroot_m), lb, ub);
-            y1[k] = (float)c1;
-            y2[k] = (float)c2;
-            if (evaluate && g < R.d && g >= R.m - 1) {
-                g1 += (double)dist_term(R.problem, y1[k]);
-                g2 += (double)dist_term(R.problem, y2[k]);
-            }
+    if (active) {
+        bool nocross = false;
+        if (R.p_c < 1.0) {
+            const W4 w = draw(R, 0u, (uint32_t)p, t, TAG_SBXPAIR);
+            nocross = ((double)w.w[0] * 0x1p-32) > R.p_c;
         }
-        if (q < 2) {
+
+        const float *x1row = R.X + (int64_t)R.slot_row[a] * R.ld;
+        const float *x2row = R.X + (int64_t)R.slot_row[b] * R.ld;
+        float *c1row = R.X + (int64_t)R.off_row[o1] * R.ld;
+        float *c2row = has2 ? R.X + (int64_t)R.off_row[o2] * R.ld : nullptr;
+        const int Q = (R.d + 3) / 4;
+        const double lb = R.lb, ub = R.ub;
+        const double np1 = R.eta_c + 1.0;
+        const int nroot = (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
+        const double nm1 = R.eta_m + 1.0;
+        const int nroot_m = (nm1 >= 1.0 && nm1 <= 64.0 && nm1 == (double)(int)nm1) ? (int)nm1 : 0;
+        double g1 = 0.0, g2 = 0.0;
+        float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
+
+        for (int q = lane; q < Q; q += S) {
+            const float4 xa = *reinterpret_cast<const float4 *>(x1row + 4 * q);
+            const float4 xb = *reinterpret_cast<const float4 *>(x2row + 4 * q);
+            const float pa[4] = {xa.x, xa.y, xa.z, xa.w};
+            const float pb[4] = {xb.x, xb.y, xb.z, xb.w};
+            const W4 w = draw(R, (uint32_t)q, (uint32_t)p, t, TAG_SBX);
+            const int g0 = 4 * q;
+            float y1[4], y2[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                pv1[k] = y1[k];
-                pv2[k] = y2[k];
+                const uint32_t word = w.w[k];
+                const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
+                double B = sgn * sbx_beta(unif24(word), R.eta_c, nroot);
+                if (((word >> 6) & 1u) || nocross) B = 1.0;
+                const double xa_ = (double)pa[k], xb_ = (double)pb[k];
+                const double up = 1.0 + B, dn = 1.0 - B;
+                double c1 = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
+                double c2 = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
+                // polynomial mutation if this gene is one of the child's sites
+                const int g = g0 + k;
+                for (int s_ = 0; s_ < n1; ++s_)
+                    if (sh_sites[seg][0][s_] == g)
+                        c1 = dclip(c1 + pm_delta(c1, lb, ub, sh_mags[seg][0][s_], R.eta_m, nroot_m), lb, ub);
+                for (int s_ = 0; s_ < n2; ++s_)
+                    if (sh_sites[seg][1][s_] == g)
+                        c2 = dclip(c2 + pm_delta(c2, lb, ub, sh_mags[seg][1][s_], R.eta_m, nroot_m), lb, ub);
+                y1[k] = (float)c1;
+                y2[k] = (float)c2;
+                if (evaluate && g < R.d && g >= R.m - 1) {
+                    g1 += (double)dist_term(R.problem, y1[k]);
+                    g2 += (double)dist_term(R.problem, y2[k]);
+                }
             }
-        }
-        *reinterpret_cast<float4 *>(c1row + g0) = make_float4(y1[0], y1[1], y1[2], y1[3]);
-        if (has2) *reinterpret_cast<float4 *>(c2row + g0) = make_float4(y2[0], y2[1], y2[2], y2[3]);
-    }
-    g1 = seg_sum<S>(g1);
-    g2 = seg_sum<S>(g2);
-    float pos1[kMaxM], pos2[kMaxM];
+            if (q < 2) {
 #pragma unroll
-    for (int k = 0; k < kMaxM - 1; ++k) {
-        pos1[k] = __shfl(pv1[k & 3], k >> 2, S);
-        pos2[k] = __shfl(pv2[k & 3], k >> 2, S);
-    }
-    if (lane == 0 && evaluate) {
-        float f[kMaxM];
-        finish_objectives(R.problem, R.m, R.d, pos1, g1, f);
-        float *F1 = R.Fm + (R.K + o1) * R.m;
-        for (int k = 0; k < R.m; ++k) F1[k] = f[k];
-        if (has2) {
-            finish_objectives(R.problem, R.m, R.d, pos2, g2, f);
-            float *F2 = R.Fm + (R.K + o2) * R.m;
-            for (int k = 0; k < R.m; ++k) F2[k] = f[k];
+                for (int k = 0; k < 4; ++k) {
+                    pv1[k] = y1[k];
+                    pv2[k] = y2[k];
+                }
+            }
+            *reinterpret_cast<float4 *>(c1row + g0) = make_float4(y1[0], y1[1], y1[2], y1[3]);
+            if (has2) *reinterpret_cast<float4 *>(c2row + g0) = make_float4(y2[0], y2[1], y2[2], y2[3]);
         }
+        g1 = seg_sum<S>(g1);
+        g2 = seg_sum<S>(g2);
+        float pos1[kMaxM], pos2[kMaxM];
+#pragma unroll
+        for (int k = 0; k < kMaxM - 1; ++k) {
+            pos1[k] = __shfl(pv1[k & 3], k >> 2, S);
+            pos2[k] = __shfl(pv2[k & 3], k >> 2, S);
+        }
+        if (lane == 0 && evaluate) {
+            // objectives; rows that take part (finite F) and their LDS minima
+            auto emit = [&](const float(&pos)[kMaxM], double gs, int64_t row) {
+                float f[kMaxM];
+                finish_objectives(R.problem, R.m, R.d, pos, gs, f);
+                float *Fr = R.Fm + row * R.m;
+                bool ok = true;
+#pragma unroll
+                for (int k = 0; k < kMaxM; ++k) {
+                    if (k < R.m) {
+                        Fr[k] = f[k];
+                        ok = ok && isfinite(f[k]);
+                    }
+                }
+                R.mvalid[row] = ok ? 1 : 0;
+                if (!ok) {
+                    atomicAdd(&R.counters[0], 1ull);
+                    return;
+                }
+#pragma unroll
+                for (int k = 0; k < kMaxM; ++k)
+                    if (k < R.m) atomicMin(&szmin[k], ord_enc(f[k]));
+            };
+            emit(pos1, g1, R.K + o1);
+            if (has2) emit(pos2, g2, R.K + o2);
+        }
+    }
+    // the workgroup's share of the ideal point: one guarded atomic per
+    // objective (values only decrease, so a stale read costs an atomic at most)
+    __syncthreads();
+    if (evaluate && threadIdx.x < R.m) {
+        const uint32_t e = szmin[threadIdx.x];
+        uint32_t *zb = zbuf(R, t);
+        if (e < *(volatile uint32_t *)&zb[threadIdx.x]) atomicMin(&zb[threadIdx.x], e);
     }
 }
 

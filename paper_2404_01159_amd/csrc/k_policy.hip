@@ -218,10 +218,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     }
     f1 = wave_sum(f1);
     f2 = wave_sum(f2);
+    const float fv[2] = {(float)(f1 / (double)R.lq_E), (float)(f2 / (double)R.lq_E)};
     if (l == 0) {
-        F[2 * q] = (float)(f1 / (double)R.lq_E);
-        F[2 * q + 1] = (float)(f2 / (double)R.lq_E);
+        F[2 * q] = fv[0];
+        F[2 * q + 1] = fv[1];
     }
+    // offspring: rows that take part and the ideal point of this generation
+    if (check_nv) child_ideal(R, *R.t_done + 1, l == 0, R.K + q, fv);
 }
 
 // Gaussian initialization of rows 0..N-1: genes 4p..4p+3 of individual i

@@ -2,7 +2,9 @@
 //
 // The paper forms the n x r angle tensor, masks it per column and takes
 // column-wise APD argmins.  Here the 2N x K cosine matrix is never stored:
-//   k_ideal   z* = column minima over the rows that take part (Alg. 1 l.3)
+// (z*, the column minima over the rows that take part (Alg. 1 l.3), is
+// reduced where the rows are produced: parents in k_prep_count, children in
+// k_offspring or k_rollout.)
 //   k_assoc   single-precision pass over (row, vector) pairs: V tiles of 32
 //             vectors sit in LDS and are broadcast to every lane; each lane
 //             holds RR rows of f' = F - z* and keeps, per vector chunk, the
@@ -15,52 +17,14 @@
 //             vector's gamma (Eq. 5); per-vector minimum APD by 64-bit atomic
 //             min on the (non-negative) double's bit pattern
 //   k_surv    the lowest row index attaining that minimum (Alg. 1 l.15)
-//   k_newpop / k_commit  slot j <- its survivor's gene row and objectives
+//   k_newpop / k_commit  slot j <- its survivor's gene row and objectives;
+//             k_commit also resets the next generation's ideal-point buffer
 // Every cross-workgroup combination is an order-free min, so the result
 // does not depend on scheduling.
 #include "rvea_dev.h"
 #include "rvea_internal.h"
 
 namespace rvea {
-
-// wave-wide minimum / maximum of an ordered encoding
-__device__ __forceinline__ uint32_t wave_min(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_max(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
-}
-
-// rows that take part: valid parent slots and all offspring with finite F
-__device__ __forceinline__ void ideal_body(const RunView &R, int64_t bx)
-{
-    __shared__ uint32_t smin[kMaxM];
-    if (threadIdx.x < kMaxM) smin[threadIdx.x] = 0xffffffffu;
-    __syncthreads();
-    const int64_t i = bx * 256 + threadIdx.x;
-    bool ok = false;
-    if (i < R.M) {
-        ok = i >= R.K || R.valid[i];
-        bool fin = true;
-        for (int k = 0; k < R.m; ++k) fin = fin && isfinite(R.Fm[i * R.m + k]);
-        if (ok && !fin) atomicAdd(&R.counters[0], 1ull);
-        ok = ok && fin;
-        R.mvalid[i] = ok ? 1 : 0;
-    }
-    for (int k = 0; k < R.m; ++k) {
-        const uint32_t e = wave_min(ok ? ord_enc(R.Fm[i * R.m + k]) : 0xffffffffu);
-        if ((threadIdx.x & 63) == 0 && e != 0xffffffffu) atomicMin(&smin[k], e);
-    }
-    __syncthreads();
-    if (threadIdx.x < R.m && smin[threadIdx.x] != 0xffffffffu)
-        atomicMin(&R.zbits[threadIdx.x], smin[threadIdx.x]);
-}
 
 // 2*eps for a row of norm nrm: |f'.v (float) - f'.v (exact)| <= 6u |f'| for
 // unit v with u = 2^-24 (rounding of f', of v and three operations); the
@@ -84,16 +48,15 @@ __device__ __forceinline__ float two_eps_dist(float S)
 template <int MD>
 __device__ __forceinline__ float negdist(const float *a, const float4 *v)
 {
-    const float w[8] = {v[0].x, v[0].y, v[0].z, v[0].w,
-                        MD > 4 ? v[1].x : 0.f, MD > 4 ? v[1].y : 0.f,
-                        MD > 4 ? v[1].z : 0.f, MD > 4 ? v[1].w : 0.f};
-    float t = a[0] - w[0];
+    float t = a[0] - v[0].x;
     float s = t * t;
-#pragma unroll
-    for (int k = 1; k < MD; ++k) {
-        t = a[k] - w[k];
-        s = fmaf(t, t, s);
-    }
+    if (MD > 1) { t = a[1] - v[0].y; s = fmaf(t, t, s); }
+    if (MD > 2) { t = a[2] - v[0].z; s = fmaf(t, t, s); }
+    if (MD > 3) { t = a[3] - v[0].w; s = fmaf(t, t, s); }
+    if (MD > 4) { t = a[4] - v[1].x; s = fmaf(t, t, s); }
+    if (MD > 5) { t = a[5] - v[1].y; s = fmaf(t, t, s); }
+    if (MD > 6) { t = a[6] - v[1].z; s = fmaf(t, t, s); }
+    if (MD > 7) { t = a[7] - v[1].w; s = fmaf(t, t, s); }
     return -s;
 }
 
@@ -128,13 +91,17 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
     const float4 *Vg = reinterpret_cast<const float4 *>(R.V32);
     for (int idx = threadIdx.x; idx < ntile * kTile * NV4; idx += 256) {
         const int v = idx / NV4;
-        sv[idx] = v < nvec ? Vg[(j0 + v) * NV4 + (idx % NV4)] : pad;
+        if (v < nvec)
+            sv[idx] = Vg[(j0 + v) * NV4 + (idx % NV4)];
+        else
+            sv[idx] = pad;
     }
     const int64_t nrows = GAMMA ? R.K : R.M;
 
     float z[MD];
+    const uint32_t *zb = zbuf(R, *R.t_done + 1);
 #pragma unroll
-    for (int k = 0; k < MD; ++k) z[k] = GAMMA ? 0.f : ord_dec(R.zbits[k]);
+    for (int k = 0; k < MD; ++k) z[k] = GAMMA ? 0.f : ord_dec(zb[k]);
     float f[RR][MD], e2[RR], cm[RR];
     uint32_t mk[RR];
     int64_t rows[RR];
@@ -271,7 +238,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
                 f[k] = R.V[i * MD + k];
                 fk = R.V32[i * (MD <= 4 ? 4 : 8) + k];
             } else {
-                const float zk = ord_dec(R.zbits[k]);
+                const float zk = ord_dec(zbuf(R, *R.t_done + 1)[k]);
                 const float Fk = R.Fm[i * MD + k];
                 f[k] = (double)Fk - (double)zk;
                 fk = Fk - zk;
@@ -545,6 +512,9 @@ __device__ __forceinline__ void commit_body(const RunView &R, int64_t bx)
         smin[threadIdx.x] = 0xffffffffu;
         smax[threadIdx.x] = 0u;
     }
+    // the next generation's ideal point starts empty (its buffer held the
+    // previous generation's, which nothing reads any more)
+    if (bx == 0 && threadIdx.x < R.m) zbuf(R, *R.t_done + 2)[threadIdx.x] = 0xffffffffu;
     __syncthreads();
     const int64_t j = bx * 256 + threadIdx.x;
     uint8_t v = 0;
@@ -576,7 +546,6 @@ __device__ __forceinline__ void commit_body(const RunView &R, int64_t bx)
 }
 
 // ------------------------------------------------------- single-run kernels
-__global__ __launch_bounds__(256) void k_ideal(RunView R) { ideal_body(R, blockIdx.x); }
 template <int MD, int RR, bool GAMMA>
 __global__ __launch_bounds__(256) void k_assoc(RunView R, int gate)
 {
@@ -594,11 +563,6 @@ __global__ __launch_bounds__(256) void k_commit(RunView R) { commit_body(R, bloc
 // ----------------------------------------------------- batched (many runs)
 // blockIdx.x is decoded into (run, local block) through the span table; for
 // the association, local = chunk * row_blocks + row_block.
-__global__ __launch_bounds__(256) void kb_ideal(const RunView *runs, const Span *sp, int n)
-{
-    const int s = find_span(sp, n, blockIdx.x);
-    ideal_body(runs[sp[s].run], blockIdx.x - sp[s].start);
-}
 template <int MD, int RR, bool GAMMA>
 __global__ __launch_bounds__(256) void kb_assoc(const RunView *runs, const Span *sp, int n)
 {
@@ -631,12 +595,6 @@ __global__ __launch_bounds__(256) void kb_commit(const RunView *runs, const Span
 
 // ------------------------------------------------------------- launchers
 static unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-hipError_t launch_select_front(const RunView &R, hipStream_t s)
-{
-    k_ideal<<<blocks(R.M, 256), 256, 0, s>>>(R);
-    return hipGetLastError();
-}
 
 #define RVEA_M_DISPATCH(MVAL, CALL)                                                          \
     switch (MVAL) {                                                                          \
@@ -730,7 +688,6 @@ hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Sp
     constexpr int RR = 4;
     const dim3 g((unsigned)blocks);
     switch (phase) {
-    case BP_IDEAL: kb_ideal<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_SURV: kb_surv<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_NEWPOP: kb_newpop<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_COMMIT: kb_commit<<<g, 256, 0, s>>>(runs, sp, n); break;

@@ -159,7 +159,6 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
         const int S = pick_segment(R.d);
         return ((R.N + 1) / 2 + (kBlock / S) - 1) / (kBlock / S);
     }
-    case BP_IDEAL:
     case BP_SURV: return (R.M + 255) / 256;
     case BP_ASSOC:
     case BP_GAMMA_ASSOC: return batch_phase_nbx(phase, R) * R.KC;

@@ -54,7 +54,7 @@ struct RunView {
     float *V32;         // K x 4 or K x 8 (padded with zeros)
     double *vn;         // K norms of V
     double *gamma;      // K
-    uint32_t *zbits;    // m ordered-encoded ideal point
+    uint32_t *zbits;    // 2 x m ordered-encoded ideal point, by generation parity
     uint32_t *rbits;    // 2m ordered-encoded survivor min / max
     float *pmax;        // KC x M chunk maxima
     uint32_t *pmask;    // KC x M candidate-tile masks
@@ -153,6 +153,49 @@ __device__ __forceinline__ float ord_dec(uint32_t e)
 {
     const uint32_t u = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
     return __uint_as_float(u);
+}
+
+// wave-wide minimum / maximum of an ordered encoding
+__device__ __forceinline__ uint32_t wave_min(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// Ideal point z* of generation gen (Alg. 1): two buffers alternate by
+// parity, so a generation's minima can be reset by the generation before and
+// the last selection's z* stays readable.
+__device__ __forceinline__ uint32_t *zbuf(const RunView &R, int64_t gen)
+{
+    return R.zbits + (gen & 1) * R.m;
+}
+
+// Child objectives f (m values) of merged row `row` (>= K): the row takes
+// part in the selection if finite (else counted), and its values lower the
+// ideal point.  Called by one lane per child; the wave's minima are merged
+// with one atomic per objective, skipped when the current value is already
+// lower (values only decrease, so a stale read only costs an atomic).
+__device__ __forceinline__ void child_ideal(const RunView &R, int64_t gen, bool has,
+                                            int64_t row, const float *f)
+{
+    bool ok = has;
+    if (has) {
+        for (int k = 0; k < R.m; ++k) ok = ok && isfinite(f[k]);
+        if (!ok) atomicAdd(&R.counters[0], 1ull);
+        R.mvalid[row] = ok ? 1 : 0;
+    }
+    uint32_t *zb = zbuf(R, gen);
+    for (int k = 0; k < R.m; ++k) {
+        const uint32_t e = wave_min(ok ? ord_enc(f[k]) : 0xffffffffu);
+        if ((threadIdx.x & 63) == 0 && e < *(volatile uint32_t *)&zb[k]) atomicMin(&zb[k], e);
+    }
 }
 
 __device__ __forceinline__ double dclip(double x, double lo, double hi)

@@ -95,7 +95,7 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
         (size_t)M * m * 4, (size_t)K * m * 4, (size_t)K * 4, (size_t)K, (size_t)M,
         (size_t)P * 2 * 4, (size_t)K * 4, 4, (size_t)(K + N) * 4, (size_t)K * m * 8,
         (size_t)K * m * 8, (size_t)K * L.stride * 4, (size_t)K * 8, (size_t)K * 8,
-        (size_t)m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
+        (size_t)2 * m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
         (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4,
         (size_t)((K + N + 255) / 256) * 4, 4, 8,
         problem == kPolicy ? (size_t)kLqFloats * 4 : 0};
@@ -363,8 +363,8 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.t_done = (int64_t *)(w + L.off[B_TDONE]);
     R.counters = (unsigned long long *)(w + L.off[B_COUNTERS]);
     R.vchanged = (int32_t *)(w + L.off[B_VCHANGED]);
-    hipError_t e = hipSuccess;
-    if (problem == kPolicy) {
+    hipError_t e = hipMemsetAsync(R.zbits, 0xff, (size_t)2 * m * 4, r->stream);
+    if (e == hipSuccess && problem == kPolicy) {
         float *lq = (float *)(w + L.off[B_LQ]);
         R.lq = lq;
         R.lq_E = sys->E;
@@ -444,7 +444,6 @@ rvea_status rvea_select(rvea_run r)
 {
     if (!r) return RVEA_EINVAL;
     if (r->phase != 1) return RVEA_ESTATE;
-    HIPCHK(r, launch_select_front(r->R, r->stream));
     rvea_status st = timed(r, 1, [&] { return launch_assoc(r->R, r->stream); }, "assoc");
     if (st != RVEA_OK) return st;
     st = timed(r, 2, [&] { return launch_rerank(r->R, r->stream); }, "rerank");
@@ -476,7 +475,6 @@ hipError_t enqueue_generation(const RunView &R, hipStream_t s, bool adapt)
     hipError_t e = launch_prepare(R, s);
     if (e == hipSuccess) e = launch_offspring(R, s);
     if (e == hipSuccess && R.problem == kPolicy) e = launch_rollout(R, s, true);
-    if (e == hipSuccess) e = launch_select_front(R, s);
     if (e == hipSuccess) e = launch_assoc(R, s);
     if (e == hipSuccess) e = launch_rerank(R, s);
     if (e == hipSuccess) e = launch_select_back(R, s);
@@ -613,6 +611,7 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
         HIPCHK(r, launch_gamma(R, r->stream, 1));
     HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemset(R.stamp, 0xff, (size_t)(R.K + R.N) * 4));
+    HIPCHK(r, hipMemset(R.zbits, 0xff, (size_t)2 * R.m * 4));
     HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     r->t = t;
     r->has_selection = false;
@@ -648,8 +647,10 @@ rvea_status rvea_get_selection(rvea_run r, float *zstar, int32_t *assoc, double 
     const RunView &R = r->R;
     HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     if (zstar) {
+        int64_t td = 0;  // the last selection's generation picks the buffer
+        HIPCHK(r, hipMemcpy(&td, R.t_done, 8, hipMemcpyDeviceToHost));
         uint32_t zb[kMaxM];
-        HIPCHK(r, hipMemcpy(zb, R.zbits, R.m * 4, hipMemcpyDeviceToHost));
+        HIPCHK(r, hipMemcpy(zb, R.zbits + (td & 1) * R.m, R.m * 4, hipMemcpyDeviceToHost));
         for (int k = 0; k < R.m; ++k) {
             const uint32_t e = zb[k];
             const uint32_t u = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
@@ -767,7 +768,6 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     HIPCHK(r, launch_prepare(R, r->stream));
     HIPCHK(r, launch_offspring(R, r->stream));
     if (R.problem == kPolicy) HIPCHK(r, launch_rollout(R, r->stream, true));
-    HIPCHK(r, launch_select_front(R, r->stream));
     hipEvent_t a = take_event(r), b = take_event(r);
     if (!a || !b) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
     struct Cand {

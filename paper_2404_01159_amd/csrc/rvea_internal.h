@@ -20,7 +20,6 @@ hipError_t launch_gamma(const RunView &R, hipStream_t s, int force);
 hipError_t launch_init(const RunView &R, hipStream_t s);
 hipError_t launch_prepare(const RunView &R, hipStream_t s);
 hipError_t launch_offspring(const RunView &R, hipStream_t s);
-hipError_t launch_select_front(const RunView &R, hipStream_t s);
 hipError_t launch_assoc(const RunView &R, hipStream_t s);
 hipError_t launch_rerank(const RunView &R, hipStream_t s);
 hipError_t launch_select_back(const RunView &R, hipStream_t s);
@@ -33,7 +32,7 @@ hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring);
 // span table (runs of the same template class: segment width for the
 // offspring, objective count for the association phases).
 enum BatchPhase {
-    BP_PREP_COUNT, BP_PREP_WRITE, BP_OFFSPRING, BP_IDEAL, BP_ASSOC, BP_RERANK, BP_SURV,
+    BP_PREP_COUNT, BP_PREP_WRITE, BP_OFFSPRING, BP_ASSOC, BP_RERANK, BP_SURV,
     BP_NEWPOP, BP_COMMIT, BP_ADAPT, BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
 int batch_phase_class(int phase, const RunView &R);       // template class of a run
