@@ -164,8 +164,10 @@ __device__ __forceinline__ double recip(double z)
 // ~ (n+1)/2 e^2 per step, leaving a few binary64 ulps
 __device__ __forceinline__ double inv_root(double a, int n)
 {
+    // callers pass a >= 1e-30 (a normal binary32), so the hardware log2 and
+    // exp2 (no denormal handling) suffice for the estimate
     const float ninv = 1.0f / (float)n;
-    double z = (double)exp2f(-log2f((float)a) * ninv);
+    double z = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf((float)a) * ninv);
     const double dn = 1.0 / (double)n;
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
@@ -440,6 +442,14 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         double g1 = 0.0, g2 = 0.0;
         float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
 
+        // mutation sites (ascending) seen through a cursor per child: this
+        // lane's quads ascend, so the next site at or after the quad is
+        // found by advancing past the other lanes' sites
+        const int32_t *st1 = sh_sites[seg][0], *st2 = sh_sites[seg][1];
+        const double *mg1 = sh_mags[seg][0], *mg2 = sh_mags[seg][1];
+        int p1 = 0, p2 = 0;
+        int nx1 = n1 > 0 ? st1[0] : INT_MAX, nx2 = n2 > 0 ? st2[0] : INT_MAX;
+
         for (int q = lane; q < Q; q += S) {
             const float4 xa = *reinterpret_cast<const float4 *>(x1row + 4 * q);
             const float4 xb = *reinterpret_cast<const float4 *>(x2row + 4 * q);
@@ -447,7 +457,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             const float pb[4] = {xb.x, xb.y, xb.z, xb.w};
             const W4 w = draw(R, (uint32_t)q, (uint32_t)p, t, TAG_SBX);
             const int g0 = 4 * q;
-            float y1[4], y2[4];
+            double c1v[4], c2v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t word = w.w[k];
@@ -456,18 +466,41 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                 if (((word >> 6) & 1u) || nocross) B = 1.0;
                 const double xa_ = (double)pa[k], xb_ = (double)pb[k];
                 const double up = 1.0 + B, dn = 1.0 - B;
-                double c1 = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
-                double c2 = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
-                // polynomial mutation if this gene is one of the child's sites
+                c1v[k] = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
+                c2v[k] = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
+            }
+            // polynomial mutation of the genes of this quad that are sites
+            while (nx1 < g0) nx1 = ++p1 < n1 ? st1[p1] : INT_MAX;
+            while (nx2 < g0) nx2 = ++p2 < n2 ? st2[p2] : INT_MAX;
+            // one pending site per lane and pass (usually a single pass), so
+            // the wave evaluates the mutation once rather than per gene
+            while (__any(nx1 < g0 + 4 || nx2 < g0 + 4)) {
+                const bool h1 = nx1 < g0 + 4;
+                if (h1 || nx2 < g0 + 4) {
+                    const int k = (h1 ? nx1 : nx2) - g0;
+                    double x = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+                        if (kk == k) x = h1 ? c1v[kk] : c2v[kk];
+                    const double mg = h1 ? mg1[p1] : mg2[p2];
+                    const double y = dclip(x + pm_delta(x, lb, ub, mg, R.eta_m, nroot_m), lb, ub);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        if (h1 && kk == k) c1v[kk] = y;
+                        if (!h1 && kk == k) c2v[kk] = y;
+                    }
+                    if (h1)
+                        nx1 = ++p1 < n1 ? st1[p1] : INT_MAX;
+                    else
+                        nx2 = ++p2 < n2 ? st2[p2] : INT_MAX;
+                }
+            }
+            float y1[4], y2[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                y1[k] = (float)c1v[k];
+                y2[k] = (float)c2v[k];
                 const int g = g0 + k;
-                for (int s_ = 0; s_ < n1; ++s_)
-                    if (sh_sites[seg][0][s_] == g)
-                        c1 = dclip(c1 + pm_delta(c1, lb, ub, sh_mags[seg][0][s_], R.eta_m, nroot_m), lb, ub);
-                for (int s_ = 0; s_ < n2; ++s_)
-                    if (sh_sites[seg][1][s_] == g)
-                        c2 = dclip(c2 + pm_delta(c2, lb, ub, sh_mags[seg][1][s_], R.eta_m, nroot_m), lb, ub);
-                y1[k] = (float)c1;
-                y2[k] = (float)c2;
                 if (evaluate && g < R.d && g >= R.m - 1) {
                     g1 += (double)dist_term(R.problem, y1[k]);
                     g2 += (double)dist_term(R.problem, y2[k]);

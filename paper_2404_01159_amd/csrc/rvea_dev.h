@@ -100,6 +100,13 @@ struct W4 {
 __device__ __forceinline__ W4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                              uint32_t k0, uint32_t k1)
 {
+    // the key schedule is computed round by round with scalar adds; a table
+    // of the 20 round keys hoisted out of the callers' loops would not fit
+    // in scalar registers and be reloaded from spill lanes every round.  The
+    // key is a run's seed, uniform over the wavefront (one run per workgroup).
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
