@@ -20,13 +20,13 @@
 namespace rvea {
 
 // ------------------------------------------------------------------ scans
-// Per generation, before the offspring: (1) every row a valid slot points
-// at is stamped with the generation number and each block of 256 slots
-// counts its valid slots; (2) each block adds the counts of the blocks
-// before it and writes its valid slots to their ascending positions, and
-// reserves room for its unstamped (free) rows with one atomic add.  The
-// order of the free rows does not matter: it only decides where each child's
-// genes are stored.
+// The population's rows are stamped with the generation that will read
+// them, and each block of 256 slots counts its valid slots, when the
+// population is written (k_newpop, or k_stamp after initialization).  Then,
+// before the offspring, each block adds the counts of the blocks before it
+// and writes its valid slots to their ascending positions, and reserves room
+// for its unstamped (free) rows with one atomic add.  The order of the free
+// rows does not matter: it only decides where each child's genes are stored.
 __device__ __forceinline__ int block_scan_256(int v, int *total)
 {
     __shared__ int wsum[4];
@@ -50,11 +50,21 @@ __device__ __forceinline__ int block_scan_256(int v, int *total)
     return before + x - v;
 }
 
-__device__ __forceinline__ void prep_count_body(const RunView &R, int64_t bx)
+// Prepare generation gen = t_done + 1 from population p = t_done (one
+// kernel): reset the selection's per-vector minima and the survivors'
+// extremes, flag the parent slots that take part (valid, finite F) with
+// their share of the ideal point, list the valid slots in ascending order
+// (block offsets from the per-block counts left by the previous generation's
+// k_newpop, or by k_stamp), and hand out free gene rows for the offspring
+// (rows whose stamp is not gen; the free-row counter was cleared by the same
+// earlier kernel).
+__device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
 {
     const int64_t j = bx * 256 + threadIdx.x;
-    const int32_t gen = (int32_t)(*R.t_done + 1);
-    // reset the selection's per-vector minima for this generation
+    const int64_t p = *R.t_done;
+    const int32_t gen = (int32_t)(p + 1);
+    const uint8_t *valid = valid_of(R, p);
+    const float *Fm = fm_of(R, p);
     if (j < R.K) {
         R.key[j] = ~0ull;
         R.surv[j] = 0x7fffffff;
@@ -63,61 +73,37 @@ __device__ __forceinline__ void prep_count_body(const RunView &R, int64_t bx)
         R.rbits[j] = 0xffffffffu;  // survivors' minimum
         R.rbits[R.m + j] = 0u;     // survivors' maximum
     }
-    // parent slots that take part in the selection (valid, finite F) and
-    // their share of this generation's ideal point
-    __shared__ uint32_t zmin[kMaxM];
-    if (threadIdx.x < kMaxM) zmin[threadIdx.x] = 0xffffffffu;
-    bool take = false;
-    if (j < R.K) {
-        take = R.valid[j] != 0;
-        bool fin = true;
-        for (int k = 0; k < R.m; ++k) fin = fin && isfinite(R.Fm[j * R.m + k]);
-        if (take && !fin) atomicAdd(&R.counters[0], 1ull);
-        take = take && fin;
-        R.mvalid[j] = take ? 1 : 0;
-    }
-    __syncthreads();
-    for (int k = 0; k < R.m; ++k) {
-        const uint32_t e = wave_min(take ? ord_enc(R.Fm[j * R.m + k]) : 0xffffffffu);
-        if ((threadIdx.x & 63) == 0 && e != 0xffffffffu) atomicMin(&zmin[k], e);
-    }
     if (j == 0) {  // Eq. 4 penalty factor m (t/t_max)^alpha of this generation
         *R.pen = (double)R.m * pow((double)gen / (double)R.t_max, R.alpha);
     }
-    int v = 0;
-    if (j < R.K && R.valid[j]) {
-        v = 1;
-        R.stamp[R.slot_row[j]] = gen;
+    __shared__ uint32_t zmin[kMaxM];
+    if (threadIdx.x < kMaxM) zmin[threadIdx.x] = 0xffffffffu;
+    const int v = (j < R.K && valid[j]) ? 1 : 0;
+    bool take = false;
+    if (j < R.K) {
+        bool fin = true;
+        for (int k = 0; k < R.m; ++k) fin = fin && isfinite(Fm[j * R.m + k]);
+        if (v && !fin) atomicAdd(&R.counters[0], 1ull);
+        take = v && fin;
+        R.mvalid[j] = take ? 1 : 0;
     }
-    const unsigned long long b = __ballot(v);
-    __shared__ int wc[4];
-    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(b);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
-        if (bx == 0) *R.freecnt = 0;
-    }
-    if (threadIdx.x < R.m && zmin[threadIdx.x] != 0xffffffffu)
-        atomicMin(&zbuf(R, gen)[threadIdx.x], zmin[threadIdx.x]);
-}
-
-__device__ __forceinline__ void prep_write_body(const RunView &R, int64_t bx)
-{
-    const int64_t j = bx * 256 + threadIdx.x;
-    const int32_t gen = (int32_t)(*R.t_done + 1);
     // offset of this block's valid slots
     int pre = 0;
-    for (int b = threadIdx.x; b < (int)bx; b += 256) pre += R.bcount[b];
-    int dummy;
-    const int zero = block_scan_256(pre, &dummy);
-    (void)zero;
-    const int offset = dummy;  // total of the per-thread partial sums
-    const int v = (j < R.K && R.valid[j]) ? 1 : 0;
+    for (int b = threadIdx.x; b < (int)bx && b < (int)((R.K + 255) / 256); b += 256)
+        pre += R.bcount[b];
+    int offset;
+    (void)block_scan_256(pre, &offset);  // block total of the partial sums
+    for (int k = 0; k < R.m; ++k) {
+        const uint32_t e = wave_min(take ? ord_enc(Fm[j * R.m + k]) : 0xffffffffu);
+        if ((threadIdx.x & 63) == 0 && e != 0xffffffffu) atomicMin(&zmin[k], e);
+    }
     int tot;
     const int pos = block_scan_256(v, &tot);
     if (v) R.vs[offset + pos] = (int32_t)j;
     const int64_t nblk = (R.K + 255) / 256;
     if (bx == nblk - 1 && threadIdx.x == 0) *R.nvalid = offset + tot;
+    if (threadIdx.x < R.m && zmin[threadIdx.x] != 0xffffffffu)
+        atomicMin(&zbuf(R, gen)[threadIdx.x], zmin[threadIdx.x]);
     // free rows of this block
     const int fr = (j < R.K + R.N && R.stamp[j] != gen) ? 1 : 0;
     int ftot;
@@ -128,8 +114,31 @@ __device__ __forceinline__ void prep_write_body(const RunView &R, int64_t bx)
     if (fr && fbase + fpos < R.N) R.off_row[fbase + fpos] = (int32_t)j;
 }
 
-__global__ __launch_bounds__(256) void k_prep_count(RunView R) { prep_count_body(R, blockIdx.x); }
-__global__ __launch_bounds__(256) void k_prep_write(RunView R) { prep_write_body(R, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_prep(RunView R) { prep_body(R, blockIdx.x); }
+
+// Row stamps, per-block valid counts and a cleared free-row counter for the
+// current population p = t_done, as k_newpop leaves them; run after
+// initialization and after the state is set from the host.
+__device__ __forceinline__ void stamp_body(const RunView &R, int64_t bx)
+{
+    const int64_t j = bx * 256 + threadIdx.x;
+    const int64_t p = *R.t_done;
+    int v = 0;
+    if (j < R.K && valid_of(R, p)[j]) {
+        v = 1;
+        R.stamp[slot_row_of(R, p)[j]] = (int32_t)(p + 1);
+    }
+    const unsigned long long b = __ballot(v);
+    __shared__ int wc[4];
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
+        if (bx == 0) *R.freecnt = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_stamp(RunView R) { stamp_body(R, blockIdx.x); }
 
 // --------------------------------------------------------------- helpers
 // z^n for a positive integer n (square and multiply, n uniform); the
@@ -285,9 +294,9 @@ __global__ __launch_bounds__(kBlock) void k_init(RunView R)
     if (lane == 0) {
         float f[kMaxM];
         finish_objectives(R.problem, R.m, R.d, pos, gsum, f);
-        for (int k = 0; k < R.m; ++k) R.Fm[i * R.m + k] = f[k];
-        R.valid[i] = 1;
-        R.slot_row[i] = (int32_t)i;
+        for (int k = 0; k < R.m; ++k) R.Fms[i * R.m + k] = f[k];  // population 0
+        R.valids[i] = 1;
+        R.slot_rows[i] = (int32_t)i;
     }
 }
 
@@ -296,9 +305,9 @@ __global__ void k_init_empty(RunView R)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + R.N;
     if (j < R.K) {
-        R.valid[j] = 0;
-        R.slot_row[j] = (int32_t)j;
-        for (int k = 0; k < R.m; ++k) R.Fm[j * R.m + k] = __int_as_float(0x7fc00000);
+        R.valids[j] = 0;  // population 0
+        R.slot_rows[j] = (int32_t)j;
+        for (int k = 0; k < R.m; ++k) R.Fms[j * R.m + k] = __int_as_float(0x7fc00000);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *R.t_done = 0;
 }
@@ -381,15 +390,17 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     const int64_t P = (R.N + 1) / 2;
     const int64_t p = bx * SEGS + seg;
     const bool active = p < P;
-    const uint32_t t = (uint32_t)(*R.t_done + 1);
+    const int64_t pop = *R.t_done;  // the parents' population
+    const uint32_t t = (uint32_t)(pop + 1);
+    float *Fm = fm_of(R, pop);
     const int64_t o1 = p, o2 = p + P;
     const bool has2 = o2 < R.N;
     const uint32_t nv = (uint32_t)*R.nvalid;
     if (nv == 0) {  // no parent left (every row was non-finite): offspring are empty
         if (active && lane == 0) {
             for (int k = 0; k < R.m; ++k) {
-                R.Fm[(R.K + o1) * R.m + k] = __int_as_float(0x7fc00000);
-                if (has2) R.Fm[(R.K + o2) * R.m + k] = __int_as_float(0x7fc00000);
+                Fm[(R.K + o1) * R.m + k] = __int_as_float(0x7fc00000);
+                if (has2) Fm[(R.K + o2) * R.m + k] = __int_as_float(0x7fc00000);
             }
             R.mvalid[R.K + o1] = 0;
             if (has2) R.mvalid[R.K + o2] = 0;
@@ -429,8 +440,9 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             nocross = ((double)w.w[0] * 0x1p-32) > R.p_c;
         }
 
-        const float *x1row = R.X + (int64_t)R.slot_row[a] * R.ld;
-        const float *x2row = R.X + (int64_t)R.slot_row[b] * R.ld;
+        const int32_t *slot_row = slot_row_of(R, pop);
+        const float *x1row = R.X + (int64_t)slot_row[a] * R.ld;
+        const float *x2row = R.X + (int64_t)slot_row[b] * R.ld;
         float *c1row = R.X + (int64_t)R.off_row[o1] * R.ld;
         float *c2row = has2 ? R.X + (int64_t)R.off_row[o2] * R.ld : nullptr;
         const int Q = (R.d + 3) / 4;
@@ -529,7 +541,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             auto emit = [&](const float(&pos)[kMaxM], double gs, int64_t row) {
                 float f[kMaxM];
                 finish_objectives(R.problem, R.m, R.d, pos, gs, f);
-                float *Fr = R.Fm + row * R.m;
+                float *Fr = Fm + row * R.m;
                 bool ok = true;
 #pragma unroll
                 for (int k = 0; k < kMaxM; ++k) {
@@ -568,15 +580,10 @@ __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
 }
 
 // ----------------------------------------------------- batched (many runs)
-__global__ __launch_bounds__(256) void kb_prep_count(const RunView *runs, const Span *sp, int n)
+__global__ __launch_bounds__(256) void kb_prep(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
-    prep_count_body(runs[sp[s].run], blockIdx.x - sp[s].start);
-}
-__global__ __launch_bounds__(256) void kb_prep_write(const RunView *runs, const Span *sp, int n)
-{
-    const int s = find_span(sp, n, blockIdx.x);
-    prep_write_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+    prep_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 template <int S>
 __global__ __launch_bounds__(kBlock) void kb_offspring(const RunView *runs, const Span *sp, int n)
@@ -616,8 +623,7 @@ hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span 
 {
     const dim3 g((unsigned)blocks);
     switch (phase) {
-    case BP_PREP_COUNT: kb_prep_count<<<g, 256, 0, s>>>(runs, sp, n); break;
-    case BP_PREP_WRITE: kb_prep_write<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_PREP: kb_prep<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_OFFSPRING:
         switch (cls) {
         case 4: kb_offspring<4><<<g, kBlock, 0, s>>>(runs, sp, n); break;
@@ -644,19 +650,22 @@ hipError_t launch_init(const RunView &R, hipStream_t s)
     const int64_t empty = R.K - R.N;
     const unsigned g = (unsigned)((empty > 0 ? empty : 1) + 255) / 256;
     k_init_empty<<<g, 256, 0, s>>>(R);
-    if (R.problem == kPolicy) {  // objectives of the initial slots by rollouts
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return launch_rollout(R, s, false);
-    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && R.problem == kPolicy)  // objectives of the initial slots by rollouts
+        e = launch_rollout(R, s, false);
+    if (e == hipSuccess) e = launch_stamp(R, s);
+    return e;
+}
+
+hipError_t launch_stamp(const RunView &R, hipStream_t s)
+{
+    k_stamp<<<(unsigned)((R.K + 255) / 256), 256, 0, s>>>(R);
     return hipGetLastError();
 }
 
 hipError_t launch_prepare(const RunView &R, hipStream_t s)
 {
-    const unsigned nb = (unsigned)((R.K + R.N + 255) / 256);
-    k_prep_count<<<nb, 256, 0, s>>>(R);
-    k_prep_write<<<nb, 256, 0, s>>>(R);
+    k_prep<<<(unsigned)((R.K + R.N + 255) / 256), 256, 0, s>>>(R);
     return hipGetLastError();
 }
 

@@ -79,10 +79,11 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Rollout evaluation of n individuals: individual q has genes in physical
-// row rows[q] and objectives F[2q], F[2q+1].  Four wavefronts per block, one
-// individual each.  With check_nv set, a generation without valid parents
-// (no offspring were written) is skipped.
+// Rollout evaluation of n individuals, one wavefront each, four per block:
+// the offspring of the current generation (offspring = 1: genes in rows
+// off_row[q], objectives into the merged rows K + q; a generation without
+// valid parents wrote no offspring and is skipped) or the initial population
+// (offspring = 0: slot q of population 0).
 //
 // Registers hold the weight matrices, b3 and the state; the dynamics
 // operands (shared by the block) and b1 (per wavefront) sit in LDS and are
@@ -95,9 +96,11 @@ struct RolloutLds {
     f32x4 b1[kRollWaves][4][4];       // b1 rows 16m+4g..+3 per (m, g)
 };
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rollout(RunView R, const int32_t *rows, float *F,
-                                                 int64_t n, int check_nv)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rollout(RunView R, int64_t n, int offspring)
 {
+    const int check_nv = offspring;
+    const int32_t *rows = offspring ? R.off_row : slot_row_of(R, 0);
+    float *F = offspring ? fm_of(R, *R.t_done) + R.K * R.m : fm_of(R, 0);
     __shared__ RolloutLds sh;
     const int wv = threadIdx.x >> 6;
     const int64_t q = (int64_t)blockIdx.x * kRollWaves + wv;
@@ -258,8 +261,8 @@ __global__ __launch_bounds__(256) void k_init_gauss(RunView R)
     for (int k = 0; k < 4; ++k) x[k] = (float)dclip(R.lq_sigma * z[k], R.lb, R.ub);
     *reinterpret_cast<float4 *>(row) = make_float4(x[0], x[1], x[2], x[3]);  // 4p+4 <= ld
     if (p == 0) {
-        R.valid[i] = 1;
-        R.slot_row[i] = (int32_t)i;
+        R.valids[i] = 1;  // population 0
+        R.slot_rows[i] = (int32_t)i;
     }
 }
 
@@ -275,9 +278,9 @@ hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring)
     const int64_t n = R.N;
     const dim3 grid((unsigned)((n + kRollWaves - 1) / kRollWaves));
     if (offspring)
-        k_rollout<<<grid, 256, 0, s>>>(R, R.off_row, R.Fm + R.K * R.m, n, 1);
+        k_rollout<<<grid, 256, 0, s>>>(R, n, 1);
     else
-        k_rollout<<<grid, 256, 0, s>>>(R, R.slot_row, R.Fm, n, 0);
+        k_rollout<<<grid, 256, 0, s>>>(R, n, 0);
     return hipGetLastError();
 }
 

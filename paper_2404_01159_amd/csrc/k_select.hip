@@ -17,8 +17,9 @@
 //             vector's gamma (Eq. 5); per-vector minimum APD by 64-bit atomic
 //             min on the (non-negative) double's bit pattern
 //   k_surv    the lowest row index attaining that minimum (Alg. 1 l.15)
-//   k_newpop / k_commit  slot j <- its survivor's gene row and objectives;
-//             k_commit also resets the next generation's ideal-point buffer
+//   k_newpop  slot j <- its survivor's gene row and objectives, written into
+//             the other buffer of the population pair (no copy-back); also
+//             the next generation's row stamps, block counts and resets
 // Every cross-workgroup combination is an order-free min, so the result
 // does not depend on scheduling.
 #include "rvea_dev.h"
@@ -100,6 +101,7 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
 
     float z[MD];
     const uint32_t *zb = zbuf(R, *R.t_done + 1);
+    const float *Fm = fm_of(R, *R.t_done);
 #pragma unroll
     for (int k = 0; k < MD; ++k) z[k] = GAMMA ? 0.f : ord_dec(zb[k]);
     float f[RR][MD], e2[RR], cm[RR];
@@ -116,7 +118,7 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
             if (GAMMA)
                 f[r][k] = ok ? R.V32[i * (NV4 * 4) + k] : 0.f;
             else
-                f[r][k] = ok ? R.Fm[i * MD + k] - z[k] : 0.f;
+                f[r][k] = ok ? Fm[i * MD + k] - z[k] : 0.f;
             n2 = fmaf(f[r][k], f[r][k], n2);
         }
         e2[r] = two_eps(sqrtf(n2));
@@ -239,7 +241,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
                 fk = R.V32[i * (MD <= 4 ? 4 : 8) + k];
             } else {
                 const float zk = ord_dec(zbuf(R, *R.t_done + 1)[k]);
-                const float Fk = R.Fm[i * MD + k];
+                const float Fk = fm_of(R, *R.t_done)[i * MD + k];
                 f[k] = (double)Fk - (double)zk;
                 fk = Fk - zk;
             }
@@ -476,9 +478,12 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     atomicMin(&R.key[bj], (unsigned long long)__double_as_longlong(a));
 }
 
+// k_surv also counts the generation: from here on t_done is the new
+// population's index (no other workgroup of this kernel reads it)
 __device__ __forceinline__ void surv_body(const RunView &R, int64_t bx)
 {
     const int64_t i = bx * 256 + threadIdx.x;
+    if (bx == 0 && threadIdx.x == 0) *R.t_done += 1;
     if (i >= R.M) return;
     const int32_t j = R.assoc[i];
     if (j < 0) return;
@@ -486,48 +491,51 @@ __device__ __forceinline__ void surv_body(const RunView &R, int64_t bx)
         atomicMin(&R.surv[j], (int32_t)i);
 }
 
+// The new population g (Alg. 1, last line) written into the other buffer of
+// each pair: slot j <- its survivor's gene row and objectives, or empty.  The
+// same pass stamps the rows generation g+1 will read, counts valid slots per
+// block (the next preparation's offsets), reduces the survivors' extremes
+// for a possible adaptation, and clears generation g+1's ideal point and
+// free-row counter.
 __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
 {
-    const int64_t j = bx * 256 + threadIdx.x;
-    if (j >= R.K) return;
-    const int32_t s = R.surv[j];
-    if (s == 0x7fffffff) {
-        R.surv[j] = -1;
-        R.valid_n[j] = 0;
-        R.row_n[j] = R.slot_row[j];
-        for (int k = 0; k < R.m; ++k) R.Fn[j * R.m + k] = __int_as_float(0x7fc00000);
-        return;
-    }
-    R.valid_n[j] = 1;
-    R.row_n[j] = s < R.K ? R.slot_row[s] : R.off_row[s - R.K];
-    for (int k = 0; k < R.m; ++k) R.Fn[j * R.m + k] = R.Fm[(int64_t)s * R.m + k];
-}
-
-// commit the new population and count the generation; also reduce the
-// survivors' per-objective extremes for a possible adaptation
-__device__ __forceinline__ void commit_body(const RunView &R, int64_t bx)
-{
     __shared__ uint32_t smin[kMaxM], smax[kMaxM];
+    __shared__ int wc[4];
+    const int64_t g = *R.t_done;  // counted by k_surv
     if (threadIdx.x < kMaxM) {
         smin[threadIdx.x] = 0xffffffffu;
         smax[threadIdx.x] = 0u;
     }
-    // the next generation's ideal point starts empty (its buffer held the
-    // previous generation's, which nothing reads any more)
-    if (bx == 0 && threadIdx.x < R.m) zbuf(R, *R.t_done + 2)[threadIdx.x] = 0xffffffffu;
+    if (bx == 0 && threadIdx.x < R.m) zbuf(R, g + 1)[threadIdx.x] = 0xffffffffu;
+    if (bx == 0 && threadIdx.x == 0) *R.freecnt = 0;
     __syncthreads();
     const int64_t j = bx * 256 + threadIdx.x;
-    uint8_t v = 0;
+    const int32_t *row0 = slot_row_of(R, g - 1);
+    const float *F0 = fm_of(R, g - 1);
+    int32_t *row1 = slot_row_of(R, g);
+    uint8_t *val1 = valid_of(R, g);
+    float *F1 = fm_of(R, g);
+    int v = 0;
+    int32_t s = 0;
     if (j < R.K) {
-        v = R.valid_n[j];
-        R.valid[j] = v;
-        R.slot_row[j] = R.row_n[j];
+        s = R.surv[j];
+        if (s == 0x7fffffff) {
+            R.surv[j] = -1;
+            val1[j] = 0;
+            row1[j] = row0[j];
+        } else {
+            v = 1;
+            const int32_t row = s < R.K ? row0[s] : R.off_row[s - R.K];
+            val1[j] = 1;
+            row1[j] = row;
+            R.stamp[row] = (int32_t)(g + 1);
+        }
     }
     for (int k = 0; k < R.m; ++k) {
         uint32_t e = 0xffffffffu;
         if (j < R.K) {
-            const float x = R.Fn[j * R.m + k];
-            R.Fm[j * R.m + k] = x;
+            const float x = v ? F0[(int64_t)s * R.m + k] : __int_as_float(0x7fc00000);
+            F1[j * R.m + k] = x;
             if (v) e = ord_enc(x);
         }
         const uint32_t lo = wave_min(e);
@@ -537,12 +545,14 @@ __device__ __forceinline__ void commit_body(const RunView &R, int64_t bx)
             atomicMax(&smax[k], hi);
         }
     }
+    const unsigned long long b = __ballot(v);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(b);
     __syncthreads();
     if (threadIdx.x < R.m) {
         if (smin[threadIdx.x] != 0xffffffffu) atomicMin(&R.rbits[threadIdx.x], smin[threadIdx.x]);
         atomicMax(&R.rbits[R.m + threadIdx.x], smax[threadIdx.x]);
     }
-    if (bx == 0 && threadIdx.x == 0) *R.t_done += 1;
+    if (threadIdx.x == 0) R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
 }
 
 // ------------------------------------------------------- single-run kernels
@@ -558,7 +568,6 @@ __global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
 }
 __global__ __launch_bounds__(256) void k_surv(RunView R) { surv_body(R, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_newpop(RunView R) { newpop_body(R, blockIdx.x); }
-__global__ __launch_bounds__(256) void k_commit(RunView R) { commit_body(R, blockIdx.x); }
 
 // ----------------------------------------------------- batched (many runs)
 // blockIdx.x is decoded into (run, local block) through the span table; for
@@ -586,11 +595,6 @@ __global__ __launch_bounds__(256) void kb_newpop(const RunView *runs, const Span
 {
     const int s = find_span(sp, n, blockIdx.x);
     newpop_body(runs[sp[s].run], blockIdx.x - sp[s].start);
-}
-__global__ __launch_bounds__(256) void kb_commit(const RunView *runs, const Span *sp, int n)
-{
-    const int s = find_span(sp, n, blockIdx.x);
-    commit_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 
 // ------------------------------------------------------------- launchers
@@ -669,7 +673,6 @@ hipError_t launch_select_back(const RunView &R, hipStream_t s)
 {
     k_surv<<<blocks(R.M, 256), 256, 0, s>>>(R);
     k_newpop<<<blocks(R.K, 256), 256, 0, s>>>(R);
-    k_commit<<<blocks(R.K, 256), 256, 0, s>>>(R);
     return hipGetLastError();
 }
 
@@ -690,7 +693,6 @@ hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Sp
     switch (phase) {
     case BP_SURV: kb_surv<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_NEWPOP: kb_newpop<<<g, 256, 0, s>>>(runs, sp, n); break;
-    case BP_COMMIT: kb_commit<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_ASSOC:
 #define RVEA_BA(MV) kb_assoc<MV, RR, false><<<g, 256, 0, s>>>(runs, sp, n)
         RVEA_M_DISPATCH(cls, RVEA_BA);

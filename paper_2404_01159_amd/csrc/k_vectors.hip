@@ -153,8 +153,7 @@ int64_t batch_phase_nbx(int phase, const RunView &R)
 int64_t batch_phase_blocks(int phase, const RunView &R)
 {
     switch (phase) {
-    case BP_PREP_COUNT:
-    case BP_PREP_WRITE: return (R.K + R.N + 255) / 256;
+    case BP_PREP: return (R.K + R.N + 255) / 256;
     case BP_OFFSPRING: {
         const int S = pick_segment(R.d);
         return ((R.N + 1) / 2 + (kBlock / S) - 1) / (kBlock / S);
@@ -165,7 +164,6 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
     case BP_RERANK: return (R.M + rerank_rows_per_wave() - 1) / rerank_rows_per_wave();
     case BP_GAMMA_RERANK: return (R.K + rerank_rows_per_wave() - 1) / rerank_rows_per_wave();
     case BP_NEWPOP:
-    case BP_COMMIT:
     case BP_ADAPT: return (R.K + 255) / 256;
     }
     return 0;

@@ -36,19 +36,20 @@ struct RunView {
     int rk;      // re-rank: rows per wave (4, 8 or 16)
 
     float *X;           // (K+N) x ld physical gene rows
-    int32_t *slot_row;  // K: physical row of each slot
+    // The population after p generations lives in buffer p & 1 of each
+    // pair below; generation p+1 reads it and writes population p+1 into
+    // the other buffer, so the new population needs no copy-back.
+    int32_t *slot_rows; // 2 x K: physical row of each slot
     int32_t *off_row;   // N: physical row of each offspring this generation
-    uint8_t *valid;     // K
-    float *Fm;          // M x m merged objectives (slots, then offspring)
-    float *Fn;          // K x m next-generation objectives
-    int32_t *row_n;     // K next slot rows
-    uint8_t *valid_n;   // K
+    uint8_t *valids;    // 2 x K
+    float *Fms;         // 2 x M x m merged objectives (slots, then offspring)
     uint8_t *mvalid;    // M: row takes part in the selection
     int32_t *parents;   // ceil(N/2) x 2 slot indices
     int32_t *vs;        // K valid slots, ascending
     int32_t *nvalid;    // 1
-    int32_t *stamp;     // K+N: generation that last found the row in use
-    int32_t *bcount;    // per-block valid-slot counts (prepare)
+    int32_t *stamp;     // K+N: the generation that will read the row (rows of
+                        // the current population carry t_done + 1)
+    int32_t *bcount;    // per-256-slot-block valid counts of the current population
     int32_t *freecnt;   // 1: free rows handed out (prepare)
     double *V0, *V;     // K x m
     float *V32;         // K x 4 or K x 8 (padded with zeros)
@@ -71,6 +72,20 @@ struct RunView {
     int lq_E, lq_T;
     double lq_sigma;    // initial genes N(0, sigma^2)
 };
+
+// buffers of population p (the state after p generations)
+__device__ __forceinline__ int32_t *slot_row_of(const RunView &R, int64_t p)
+{
+    return R.slot_rows + (p & 1) * R.K;
+}
+__device__ __forceinline__ uint8_t *valid_of(const RunView &R, int64_t p)
+{
+    return R.valids + (p & 1) * R.K;
+}
+__device__ __forceinline__ float *fm_of(const RunView &R, int64_t p)
+{
+    return R.Fms + (p & 1) * R.M * R.m;
+}
 
 // One run's share of a batched launch: blocks [start, next start) belong to
 // run `run` of the device run table; nbx is the row-block count of a 2-D

@@ -29,7 +29,7 @@ struct Layout {
 };
 
 enum Buf {
-    B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_FN, B_ROWN, B_VALIDN, B_MVALID, B_PARENTS, B_VS,
+    B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_MVALID, B_PARENTS, B_VS,
     B_NVALID, B_STAMP, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
     B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_BCOUNT, B_FREECNT, B_PEN,
     B_LQ, B_COUNT
@@ -91,8 +91,8 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
     L.KC = (int)((K + cs - 1) / cs);
     const int64_t P = (N + 1) / 2;
     const size_t sz[B_COUNT] = {
-        (size_t)(K + N) * L.ld * 4, (size_t)K * 4, (size_t)N * 4, (size_t)K,
-        (size_t)M * m * 4, (size_t)K * m * 4, (size_t)K * 4, (size_t)K, (size_t)M,
+        (size_t)(K + N) * L.ld * 4, (size_t)2 * K * 4, (size_t)N * 4, (size_t)2 * K,
+        (size_t)2 * M * m * 4, (size_t)M,
         (size_t)P * 2 * 4, (size_t)K * 4, 4, (size_t)(K + N) * 4, (size_t)K * m * 8,
         (size_t)K * m * 8, (size_t)K * L.stride * 4, (size_t)K * 8, (size_t)K * 8,
         (size_t)2 * m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
@@ -332,13 +332,10 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.rk = default_rerank_rows(K + N);
     char *w = (char *)workspace;
     R.X = (float *)(w + L.off[B_X]);
-    R.slot_row = (int32_t *)(w + L.off[B_SLOT]);
+    R.slot_rows = (int32_t *)(w + L.off[B_SLOT]);
     R.off_row = (int32_t *)(w + L.off[B_OFF]);
-    R.valid = (uint8_t *)(w + L.off[B_VALID]);
-    R.Fm = (float *)(w + L.off[B_FM]);
-    R.Fn = (float *)(w + L.off[B_FN]);
-    R.row_n = (int32_t *)(w + L.off[B_ROWN]);
-    R.valid_n = (uint8_t *)(w + L.off[B_VALIDN]);
+    R.valids = (uint8_t *)(w + L.off[B_VALID]);
+    R.Fms = (float *)(w + L.off[B_FM]);
     R.mvalid = (uint8_t *)(w + L.off[B_MVALID]);
     R.parents = (int32_t *)(w + L.off[B_PARENTS]);
     R.vs = (int32_t *)(w + L.off[B_VS]);
@@ -558,28 +555,51 @@ rvea_status copy_rows(rvea_run r, const std::vector<int32_t> &rows, float *dst)
 
 }  // namespace
 
+namespace {
+
+// the population buffers of population p (completed generations)
+int32_t *slot_rows_at(const RunView &R, int64_t p) { return R.slot_rows + (p & 1) * R.K; }
+uint8_t *valids_at(const RunView &R, int64_t p) { return R.valids + (p & 1) * R.K; }
+float *fm_at(const RunView &R, int64_t p) { return R.Fms + (p & 1) * R.M * R.m; }
+
+// completed generations as the device counts them (after a synchronize)
+rvea_status device_t(rvea_run r, int64_t *t)
+{
+    HIPCHK(r, hipMemcpy(t, r->R.t_done, 8, hipMemcpyDeviceToHost));
+    return RVEA_OK;
+}
+
+// the population whose merged buffer holds this generation's offspring:
+// the parents' (before rvea_select counts the generation, after it one less)
+int64_t offspring_pop(rvea_run r, int64_t td) { return r->phase == 2 ? td - 1 : td; }
+
+}  // namespace
+
 rvea_status rvea_get_state(rvea_run r, float *X, float *F, uint8_t *valid, double *V,
                            double *V0, double *gamma, int64_t *t)
 {
     if (!r) return RVEA_EINVAL;
     const RunView &R = r->R;
     HIPCHK(r, hipStreamSynchronize(active_stream(r)));
+    int64_t td = 0;
+    rvea_status st0 = device_t(r, &td);
+    if (st0 != RVEA_OK) return st0;
     std::vector<uint8_t> vh(R.K);
-    HIPCHK(r, hipMemcpy(vh.data(), R.valid, R.K, hipMemcpyDeviceToHost));
+    HIPCHK(r, hipMemcpy(vh.data(), valids_at(R, td), R.K, hipMemcpyDeviceToHost));
     if (valid) std::memcpy(valid, vh.data(), R.K);
     if (X) {
         std::vector<int32_t> rows(R.K);
-        HIPCHK(r, hipMemcpy(rows.data(), R.slot_row, R.K * 4, hipMemcpyDeviceToHost));
+        HIPCHK(r, hipMemcpy(rows.data(), slot_rows_at(R, td), R.K * 4, hipMemcpyDeviceToHost));
         rvea_status st = copy_rows(r, rows, X);
         if (st != RVEA_OK) return st;
         for (int64_t j = 0; j < R.K; ++j)
             if (!vh[j]) std::memset(X + j * R.d, 0, (size_t)R.d * 4);
     }
-    if (F) HIPCHK(r, hipMemcpy(F, R.Fm, (size_t)R.K * R.m * 4, hipMemcpyDeviceToHost));
+    if (F) HIPCHK(r, hipMemcpy(F, fm_at(R, td), (size_t)R.K * R.m * 4, hipMemcpyDeviceToHost));
     if (V) HIPCHK(r, hipMemcpy(V, R.V, (size_t)R.K * R.m * 8, hipMemcpyDeviceToHost));
     if (V0) HIPCHK(r, hipMemcpy(V0, R.V0, (size_t)R.K * R.m * 8, hipMemcpyDeviceToHost));
     if (gamma) HIPCHK(r, hipMemcpy(gamma, R.gamma, (size_t)R.K * 8, hipMemcpyDeviceToHost));
-    if (t) HIPCHK(r, hipMemcpy(t, R.t_done, 8, hipMemcpyDeviceToHost));
+    if (t) *t = td;
     return check_counters(r);
 }
 
@@ -598,9 +618,9 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
         rows[j] = (int32_t)j;
         vv[j] = valid[j] ? 1 : 0;
     }
-    HIPCHK(r, hipMemcpy(R.slot_row, rows.data(), R.K * 4, hipMemcpyHostToDevice));
-    HIPCHK(r, hipMemcpy(R.valid, vv.data(), R.K, hipMemcpyHostToDevice));
-    HIPCHK(r, hipMemcpy(R.Fm, F, (size_t)R.K * R.m * 4, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(slot_rows_at(R, t), rows.data(), R.K * 4, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(valids_at(R, t), vv.data(), R.K, hipMemcpyHostToDevice));
+    HIPCHK(r, hipMemcpy(fm_at(R, t), F, (size_t)R.K * R.m * 4, hipMemcpyHostToDevice));
     if (V) {
         HIPCHK(r, hipMemcpy(R.V, V, (size_t)R.K * R.m * 8, hipMemcpyHostToDevice));
         HIPCHK(r, launch_vec_aux(R, r->stream));
@@ -612,6 +632,8 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
     HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemset(R.stamp, 0xff, (size_t)(R.K + R.N) * 4));
     HIPCHK(r, hipMemset(R.zbits, 0xff, (size_t)2 * R.m * 4));
+    HIPCHK(r, hipDeviceSynchronize());
+    HIPCHK(r, launch_stamp(R, r->stream));
     HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     r->t = t;
     r->has_selection = false;
@@ -630,9 +652,13 @@ rvea_status rvea_get_offspring(rvea_run r, float *X, float *F, int32_t *parents)
         rvea_status st = copy_rows(r, rows, X);
         if (st != RVEA_OK) return st;
     }
-    if (F)
-        HIPCHK(r, hipMemcpy(F, R.Fm + R.K * R.m, (size_t)R.N * R.m * 4,
-                            hipMemcpyDeviceToHost));
+    if (F) {
+        int64_t td = 0;
+        rvea_status st = device_t(r, &td);
+        if (st != RVEA_OK) return st;
+        HIPCHK(r, hipMemcpy(F, fm_at(R, offspring_pop(r, td)) + R.K * R.m,
+                            (size_t)R.N * R.m * 4, hipMemcpyDeviceToHost));
+    }
     if (parents)
         HIPCHK(r, hipMemcpy(parents, R.parents, (size_t)((R.N + 1) / 2) * 8,
                             hipMemcpyDeviceToHost));
@@ -673,8 +699,12 @@ rvea_status rvea_get_rows(rvea_run r, int offspring, const int64_t *idx, int64_t
     for (int64_t q = 0; q < n; ++q)
         if (idx[q] < 0 || idx[q] >= lim) return RVEA_EINVAL;
     HIPCHK(r, hipStreamSynchronize(active_stream(r)));
+    int64_t td = 0;
+    rvea_status st0 = device_t(r, &td);
+    if (st0 != RVEA_OK) return st0;
+    const int64_t pop = offspring ? offspring_pop(r, td) : td;
     std::vector<int32_t> map(lim);
-    HIPCHK(r, hipMemcpy(map.data(), offspring ? R.off_row : R.slot_row, lim * 4,
+    HIPCHK(r, hipMemcpy(map.data(), offspring ? R.off_row : slot_rows_at(R, td), lim * 4,
                         hipMemcpyDeviceToHost));
     for (int64_t q = 0; q < n; ++q) {
         const int64_t i = idx[q];
@@ -682,7 +712,7 @@ rvea_status rvea_get_rows(rvea_run r, int offspring, const int64_t *idx, int64_t
             HIPCHK(r, hipMemcpy(X + q * R.d, R.X + (size_t)map[i] * R.ld, (size_t)R.d * 4,
                                 hipMemcpyDeviceToHost));
         if (F)
-            HIPCHK(r, hipMemcpy(F + q * R.m, R.Fm + ((offspring ? R.K : 0) + i) * R.m,
+            HIPCHK(r, hipMemcpy(F + q * R.m, fm_at(R, pop) + ((offspring ? R.K : 0) + i) * R.m,
                                 (size_t)R.m * 4, hipMemcpyDeviceToHost));
     }
     return check_counters(r);
@@ -842,6 +872,9 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     r->pool.push_back(a);
     r->pool.push_back(b);
     HIPCHK(r, hipMemcpy(R.counters, saved, sizeof saved, hipMemcpyHostToDevice));
+    // the trial's preparation handed out free rows: the real one starts over
+    HIPCHK(r, hipMemsetAsync(R.freecnt, 0, 4, r->stream));
+    HIPCHK(r, hipStreamSynchronize(r->stream));
     drop_graphs(r);            // captured with the old launch shapes
     r->has_selection = false;  // the trial overwrote the last selection's buffers
     if (out) {

@@ -19,6 +19,9 @@ hipError_t launch_vec_aux(const RunView &R, hipStream_t s);
 hipError_t launch_gamma(const RunView &R, hipStream_t s, int force);
 hipError_t launch_init(const RunView &R, hipStream_t s);
 hipError_t launch_prepare(const RunView &R, hipStream_t s);
+// row stamps and per-block valid counts of the current population (after
+// initialization or a host-set state)
+hipError_t launch_stamp(const RunView &R, hipStream_t s);
 hipError_t launch_offspring(const RunView &R, hipStream_t s);
 hipError_t launch_assoc(const RunView &R, hipStream_t s);
 hipError_t launch_rerank(const RunView &R, hipStream_t s);
@@ -32,8 +35,8 @@ hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring);
 // span table (runs of the same template class: segment width for the
 // offspring, objective count for the association phases).
 enum BatchPhase {
-    BP_PREP_COUNT, BP_PREP_WRITE, BP_OFFSPRING, BP_ASSOC, BP_RERANK, BP_SURV,
-    BP_NEWPOP, BP_COMMIT, BP_ADAPT, BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
+    BP_PREP, BP_OFFSPRING, BP_ASSOC, BP_RERANK, BP_SURV,
+    BP_NEWPOP, BP_ADAPT, BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
 int batch_phase_class(int phase, const RunView &R);       // template class of a run
 int64_t batch_phase_blocks(int phase, const RunView &R);  // its block count
