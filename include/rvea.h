@@ -221,7 +221,8 @@ rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *laun
  * computation, Eq. 2) can run with 1, 2 or 4 rows per lane and with vector
  * chunks of 32..1024 vectors (at least the default length; fewer chunks mean
  * fewer per-chunk partials to write and re-read), and its binary64 re-rank
- * with 4, 8 or 16 rows per wavefront.  rvea_autotune draws the
+ * with 4, 8 or 16 rows per wavefront.  Association shapes are timed together
+ * with the re-rank that reads their partials.  rvea_autotune draws the
  * next generation's offspring and ideal point without committing anything,
  * times every candidate on them with HIP events (best of three launches) and
  * keeps the fastest for the rest of the run (the adaptation's gamma pass
@@ -235,8 +236,8 @@ typedef struct rvea_tuning {
     int32_t chunk_vectors;      /* association: chosen chunk length */
     int32_t rerank_rows;        /* binary64 re-rank: chosen rows per wavefront (4, 8, 16) */
     int32_t candidates;         /* configurations timed */
-    double assoc_us;            /* best time of the chosen association configuration */
-    double default_us;          /* best time of the default one */
+    double assoc_us;            /* association + re-rank, chosen shape (best of three) */
+    double default_us;          /* association + re-rank, default shape */
     double rerank_us;           /* best time of the chosen re-rank configuration */
     double rerank_default_us;   /* best time of the default one */
 } rvea_tuning;

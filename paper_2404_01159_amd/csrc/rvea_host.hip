@@ -802,7 +802,7 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     if (!a || !b) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
     struct Cand {
         int rr, cs;
-        float ms;
+        float ms;  // association + re-rank
     };
     std::vector<Cand> cands;
     for (int rr : {4, 2, 1})
@@ -817,11 +817,15 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
         R.CS = c.cs;
         R.KC = (int)((R.K + c.cs - 1) / c.cs);
         if (R.KC > KC0) continue;  // the workspace holds KC0 chunk partials
+        // the chunk count also sets the re-rank's work (partials per row),
+        // so each candidate is timed with the re-rank that follows it
         HIPCHK(r, launch_assoc(R, r->stream));  // warm
+        HIPCHK(r, launch_rerank(R, r->stream));
         float best = 1e30f;
         for (int rep_ = 0; rep_ < 3; ++rep_) {
             HIPCHK(r, hipEventRecord(a, r->stream));
             HIPCHK(r, launch_assoc(R, r->stream));
+            HIPCHK(r, launch_rerank(R, r->stream));
             HIPCHK(r, hipEventRecord(b, r->stream));
             HIPCHK(r, hipEventSynchronize(b));
             float ms = 0.f;
