@@ -168,29 +168,31 @@ __device__ __forceinline__ double recip(double z)
     return r;
 }
 
-// a^(-1/n), a in (0, 2], n a positive integer: single-precision estimate and
-// two Newton steps on z^-n = a (z <- z (1 + (1 - a z^n)/n)), error
-// ~ (n+1)/2 e^2 per step, leaving a few binary64 ulps
-__device__ __forceinline__ double inv_root(double a, int n)
+// a^(-1/n), a in (0, 2], n a positive integer (NR > 0: n = NR fixed at
+// compile time, else n = nrt).  A single-precision estimate z (relative error
+// below 1e-6) and one third-order correction: with e = 1 - a z^n the root is
+// z (1 - e)^(-1/n) = z (1 + e/n + (n+1)/(2n^2) e^2 + O(e^3)), and the O(e^3)
+// remainder is below 1e-18.  The rounding of a z^n (about n/2 binary64 ulps)
+// enters divided by n, so the result is within a few binary64 ulps.
+template <int NR>
+__device__ __forceinline__ double inv_root(double a, int nrt)
 {
+    const int n = NR > 0 ? NR : nrt;
     // callers pass a >= 1e-30 (a normal binary32), so the hardware log2 and
     // exp2 (no denormal handling) suffice for the estimate
     const float ninv = 1.0f / (float)n;
-    double z = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf((float)a) * ninv);
+    const double z = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf((float)a) * ninv);
+    const double e = fma(-a, ipow(z, n), 1.0);
     const double dn = 1.0 / (double)n;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-a, ipow(z, n), 1.0);
-        z = fma(z * e, dn, z);
-    }
-    return z;
+    const double c2 = (double)(n + 1) / (2.0 * (double)n * (double)n);
+    return fma(z * e, fma(e, c2, dn), z);
 }
 
 // polynomial mutation shift Delta of Appendix B, binary64:
 //   M < 1/2: (ub-lb) [(2M + (1-2M)(1-d1)^(xi+1))^(1/(xi+1)) - 1]
 //   M > 1/2: (ub-lb) [1 - (2(1-M) + 2(M-1/2)(1-d2)^(xi+1))^(1/(xi+1))]
 // d1 = (x-lb)/(ub-lb), d2 = (ub-x)/(ub-lb).  For integer n = xi+1 the
-// power is a product and the root the Newton root above; otherwise pow().
+// power is a product and the root the one above; otherwise pow().
 __device__ __attribute__((noinline)) double pm_delta_pow(double x, double lb, double ub,
                                                         double mm, double xi)
 {
@@ -209,10 +211,14 @@ __device__ __attribute__((noinline)) double pm_delta_pow(double x, double lb, do
     return 0.0;
 }
 
+// NR > 0: n = xi + 1 = NR fixed at compile time; else n = nrt (0: not an
+// integer in [1, 64], pow())
+template <int NR>
 __device__ __forceinline__ double pm_delta(double x, double lb, double ub, double mm, double xi,
-                                           int n)
+                                           int nrt)
 {
-    if (n <= 0) return pm_delta_pow(x, lb, ub, mm, xi);
+    const int n = NR > 0 ? NR : nrt;
+    if (NR <= 0 && n <= 0) return pm_delta_pow(x, lb, ub, mm, xi);
     if (mm == 0.5) return 0.0;
     const double span = ub - lb;
     const bool lo = mm < 0.5;
@@ -220,7 +226,7 @@ __device__ __forceinline__ double pm_delta(double x, double lb, double ub, doubl
     const double base = lo ? 2.0 * mm + (1.0 - 2.0 * mm) * ipow(1.0 - dd, n)
                            : 2.0 * (1.0 - mm) + 2.0 * (mm - 0.5) * ipow(1.0 - dd, n);
     if (base > 0.0 && base < 1e-30) return pm_delta_pow(x, lb, ub, mm, xi);  // below float range
-    const double r = base > 0.0 ? recip(inv_root(base, n)) : 0.0;
+    const double r = base > 0.0 ? recip(inv_root<NR>(base, n)) : 0.0;
     return lo ? span * (r - 1.0) : span * (1.0 - r);
 }
 
@@ -232,18 +238,21 @@ __device__ __attribute__((noinline)) double sbx_beta_pow(double mc, double eta)
 }
 
 // SBX spread factor (Appendix B): (2 M_c)^(1/(eta+1)) below 1/2,
-// (2 - 2 M_c)^(-1/(eta+1)) above, in binary64.  When eta+1 is a small
-// integer n the root a^(-1/n) starts from a single-precision estimate and
-// takes two Newton steps on z^-n = a (z <- z (1 + (1 - a z^n)/n), division
-// free, error ~ (n+1)/2 e^2 per step), which leaves it within a few binary64
-// ulps; other eta use pow().
-__device__ __forceinline__ double sbx_beta(double mc, double eta, int n)
+// (2 - 2 M_c)^(-1/(eta+1)) above, in binary64.  When n = eta+1 is a small
+// integer (NR > 0: n = NR fixed at compile time, else n = nrt > 0) the root
+// a^(-1/n) is inv_root's, and 1/root below 1/2; other eta use pow().  Branch
+// free: M_c = 0 (spread 0) computes the root of 1 and discards it.
+template <int NR>
+__device__ __forceinline__ double sbx_beta(double mc, double eta, int nrt)
 {
-    if (n > 0) {
-        if (mc == 0.0) return 0.0;
-        const double a = mc < 0.5 ? 2.0 * mc : 2.0 - 2.0 * mc;
-        const double z = inv_root(a, n);
-        return mc < 0.5 ? recip(z) : z;
+    if (NR > 0 || nrt > 0) {
+        const bool lo = mc < 0.5;
+        const bool zero = mc == 0.0;
+        double a = lo ? 2.0 * mc : 2.0 - 2.0 * mc;
+        a = zero ? 1.0 : a;
+        const double z = inv_root<NR>(a, nrt);
+        const double b = lo ? recip(z) : z;
+        return zero ? 0.0 : b;
     }
     return sbx_beta_pow(mc, eta);
 }
@@ -377,7 +386,21 @@ __device__ void draw_sites(const RunView &R, uint32_t t, int64_t o1, int64_t o2,
     *n2 = cnt2 < kMaxSites ? cnt2 : kMaxSites;
 }
 
-template <int S>
+// Distance term of one gene: DK = 1 multimodal, 2 quadratic, -1 chosen by
+// the problem id at run time.
+template <int DK>
+__device__ __forceinline__ float dterm(int problem, float z)
+{
+    return dist_term(DK > 0 ? DK : problem, z);
+}
+
+// One segment of S lanes per parent pair.  NR > 0 compiles in the root index
+// n = eta + 1 = NR of both SBX and mutation; DK = 0 skips evaluation (the
+// policy problem has its own rollout kernel), DK > 0 fixes the distance term
+// and DK = -1 reads problem and indices from the run (the batched kernel).
+// Every variant takes the same arithmetic steps, so results do not depend on
+// which one ran.
+template <int S, int NR, int DK>
 __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
 {
     constexpr int SEGS = kBlock / S;
@@ -431,8 +454,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                           sh_sites[seg][1], sh_mags[seg][1], &n1, &n2);
     }
     __syncthreads();
-    // the policy problem is evaluated by its own rollout kernel afterwards
-    const bool evaluate = R.problem != kPolicy;
+    const bool evaluate = DK > 0 || (DK < 0 && R.problem != kPolicy);
     if (active) {
         bool nocross = false;
         if (R.p_c < 1.0) {
@@ -448,9 +470,12 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         const int Q = (R.d + 3) / 4;
         const double lb = R.lb, ub = R.ub;
         const double np1 = R.eta_c + 1.0;
-        const int nroot = (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
+        const int nroot =
+            NR > 0 ? NR : (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
         const double nm1 = R.eta_m + 1.0;
-        const int nroot_m = (nm1 >= 1.0 && nm1 <= 64.0 && nm1 == (double)(int)nm1) ? (int)nm1 : 0;
+        const int nroot_m =
+            NR > 0 ? NR : (nm1 >= 1.0 && nm1 <= 64.0 && nm1 == (double)(int)nm1) ? (int)nm1 : 0;
+        const int mlo = R.m - 1;  // first distance variable
         double g1 = 0.0, g2 = 0.0;
         float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
 
@@ -474,7 +499,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             for (int k = 0; k < 4; ++k) {
                 const uint32_t word = w.w[k];
                 const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
-                double B = sgn * sbx_beta(unif24(word), R.eta_c, nroot);
+                double B = sgn * sbx_beta<NR>(unif24(word), R.eta_c, nroot);
                 if (((word >> 6) & 1u) || nocross) B = 1.0;
                 const double xa_ = (double)pa[k], xb_ = (double)pb[k];
                 const double up = 1.0 + B, dn = 1.0 - B;
@@ -495,7 +520,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                     for (int kk = 0; kk < 4; ++kk)
                         if (kk == k) x = h1 ? c1v[kk] : c2v[kk];
                     const double mg = h1 ? mg1[p1] : mg2[p2];
-                    const double y = dclip(x + pm_delta(x, lb, ub, mg, R.eta_m, nroot_m), lb, ub);
+                    const double y = dclip(x + pm_delta<NR>(x, lb, ub, mg, R.eta_m, nroot_m), lb, ub);
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         if (h1 && kk == k) c1v[kk] = y;
@@ -512,11 +537,27 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             for (int k = 0; k < 4; ++k) {
                 y1[k] = (float)c1v[k];
                 y2[k] = (float)c2v[k];
-                const int g = g0 + k;
-                if (evaluate && g < R.d && g >= R.m - 1) {
-                    g1 += (double)dist_term(R.problem, y1[k]);
-                    g2 += (double)dist_term(R.problem, y2[k]);
+            }
+            if (evaluate) {
+                // the quad's distance terms, summed in single precision and
+                // added to the double sums; positions and padding count 0
+                float t1[4], t2[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    t1[k] = dterm<DK>(R.problem, y1[k]);
+                    t2[k] = dterm<DK>(R.problem, y2[k]);
                 }
+                if (g0 < mlo || g0 + 4 > R.d) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (g0 + k < mlo || g0 + k >= R.d) {
+                            t1[k] = 0.0f;
+                            t2[k] = 0.0f;
+                        }
+                    }
+                }
+                g1 += (double)((t1[0] + t1[1]) + (t1[2] + t1[3]));
+                g2 += (double)((t2[0] + t2[1]) + (t2[2] + t2[3]));
             }
             if (q < 2) {
 #pragma unroll
@@ -573,10 +614,10 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     }
 }
 
-template <int S>
+template <int S, int NR, int DK>
 __global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
 {
-    offspring_body<S>(R, blockIdx.x);
+    offspring_body<S, NR, DK>(R, blockIdx.x);
 }
 
 // ----------------------------------------------------- batched (many runs)
@@ -589,7 +630,7 @@ template <int S>
 __global__ __launch_bounds__(kBlock) void kb_offspring(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
-    offspring_body<S>(runs[sp[s].run], blockIdx.x - sp[s].start);
+    offspring_body<S, 0, -1>(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 
 // ------------------------------------------------------------- launchers
@@ -669,11 +710,34 @@ hipError_t launch_prepare(const RunView &R, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_offspring(const RunView &R, hipStream_t s)
+template <int NR, int DK>
+void launch_offspring_as(const RunView &R, hipStream_t s)
 {
     const int S = pick_segment(R.d);
     const int64_t P = (R.N + 1) / 2;
-    RVEA_SEG_DISPATCH(S, k_offspring, P, s, R);
+    switch (S) {
+    case 4: k_offspring<4, NR, DK><<<dim3((unsigned)((P + 63) / 64)), kBlock, 0, s>>>(R); break;
+    case 8: k_offspring<8, NR, DK><<<dim3((unsigned)((P + 31) / 32)), kBlock, 0, s>>>(R); break;
+    case 16: k_offspring<16, NR, DK><<<dim3((unsigned)((P + 15) / 16)), kBlock, 0, s>>>(R); break;
+    case 32: k_offspring<32, NR, DK><<<dim3((unsigned)((P + 7) / 8)), kBlock, 0, s>>>(R); break;
+    default: k_offspring<64, NR, DK><<<dim3((unsigned)((P + 3) / 4)), kBlock, 0, s>>>(R); break;
+    }
+}
+
+hipError_t launch_offspring(const RunView &R, hipStream_t s)
+{
+    // the default distribution indices (eta_c = eta_m = 20) get the root
+    // index compiled in; any other run takes the general kernel
+    if (R.eta_c == 20.0 && R.eta_m == 20.0) {
+        if (R.problem == kPolicy)
+            launch_offspring_as<21, 0>(R, s);
+        else if (R.problem == 2)
+            launch_offspring_as<21, 2>(R, s);
+        else
+            launch_offspring_as<21, 1>(R, s);
+    } else {
+        launch_offspring_as<0, -1>(R, s);
+    }
     return hipGetLastError();
 }
 
