@@ -106,6 +106,7 @@ def policy_leg(a):
     warm.close()
     run = mk(C["seed"])
     tuning = run.autotune() if not a.no_autotune else None
+    run.prepare(C["gens"])
     run.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -184,7 +185,7 @@ def serving_legs(a):
                                       ticks=srv.ticks, arena_gib=total / (1 << 30))
     del be, srv
     torch.cuda.synchronize()
-    # one run at a time, plain single-run path (graph per generation)
+    # one run at a time, plain single-run path (multi-generation graphs)
     t0 = time.perf_counter()
     for r in sat:
         run = P.Run(r.problem, r.m, r.d, r.N, r.K, seed=r.seed,
@@ -260,6 +261,7 @@ def main():
     run = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"],
                 params=prm, device="cuda:0")
     tuning = run.autotune() if not a.no_autotune else None
+    run.prepare(a.steps)  # graph capture outside the timed region
     run.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

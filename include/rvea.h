@@ -155,10 +155,19 @@ rvea_status rvea_select(rvea_run run);
 rvea_status rvea_adapt(rvea_run run);
 
 /* n x (rvea_step, rvea_select, rvea_adapt).  Unless disabled with
- * rvea_set_graphs or while kernel timing is on, each generation is one
- * launch of a HIP graph captured once per run (a second graph holds the
- * adapting generation).  Results are identical either way. */
+ * rvea_set_graphs or while kernel timing is on, up to 16 consecutive
+ * generations (a multiple of the adaptation period when that is at most 16)
+ * go out as one launch of a HIP graph, captured on first use for that length
+ * and those adapting positions; a run keeps at most 8 such graphs.  Results
+ * are identical either way. */
 rvea_status rvea_run_generations(rvea_run run, int n);
+
+/* Captures, without running anything, the graphs that
+ * rvea_run_generations(run, n) would launch from the current generation, so
+ * that the capture cost is not paid inside a latency- or time-critical call.
+ * Nothing to do when graphs are disabled.  RVEA_ESTATE between rvea_step and
+ * rvea_adapt or while the run belongs to a batch. */
+rvea_status rvea_prepare_generations(rvea_run run, int n);
 
 /* 1 (default) = rvea_run_generations replays captured HIP graphs, 0 = it
  * launches every kernel individually. */

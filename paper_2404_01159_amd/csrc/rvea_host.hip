@@ -127,10 +127,16 @@ struct rvea_run_s {
     };
     std::vector<Ev> events;
     std::vector<hipEvent_t> pool;
-    // whole-generation graphs: [0] step+select, [1] step+select+adapt
+    // captured runs of consecutive generations, keyed by their length and
+    // which of them adapt (bit k: the k-th generation of the run)
+    struct Graph {
+        int len;
+        uint64_t adapt;
+        hipGraph_t g;
+        hipGraphExec_t x;
+    };
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::vector<Graph> graphs;
     bool use_graphs = true;
     rvea_batch batch = nullptr;  // non-null while admitted to a batch
 };
@@ -479,38 +485,98 @@ hipError_t enqueue_generation(const RunView &R, hipStream_t s, bool adapt)
     return e;
 }
 
-rvea_status build_graphs(rvea_run r)
+constexpr int kGraphGens = 16;   // generations per graph launch at most
+constexpr size_t kGraphCache = 8;  // captured graphs kept per run
+
+void drop_graphs(rvea_run r)
 {
-    if (r->gexec[0] && r->gexec[1]) return RVEA_OK;
+    for (auto &g : r->graphs) {
+        if (g.x) (void)hipGraphExecDestroy(g.x);
+        if (g.g) (void)hipGraphDestroy(g.g);
+    }
+    r->graphs.clear();
+}
+
+// the graph of len consecutive generations whose adapting ones are the set
+// bits of adapt, captured on first use
+rvea_status graph_for(rvea_run r, int len, uint64_t adapt, hipGraphExec_t *out)
+{
+    for (auto &g : r->graphs) {
+        if (g.len == len && g.adapt == adapt) {
+            *out = g.x;
+            return RVEA_OK;
+        }
+    }
+    if (r->graphs.size() >= kGraphCache) {  // none of them may still be running
+        HIPCHK(r, hipStreamSynchronize(r->stream));
+        drop_graphs(r);
+    }
     if (!r->cap_stream)
         HIPCHK(r, hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking));
-    for (int v = 0; v < 2; ++v) {
-        HIPCHK(r, hipStreamBeginCapture(r->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_generation(r->R, r->cap_stream, v == 1);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(r->cap_stream, &g);
-        if (e != hipSuccess) return fail(r, e, "graph capture");
-        if (e2 != hipSuccess) return fail(r, e2, "hipStreamEndCapture");
-        r->graph[v] = g;
-        HIPCHK(r, hipGraphInstantiate(&r->gexec[v], g, nullptr, nullptr, 0));
+    HIPCHK(r, hipStreamBeginCapture(r->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < len && e == hipSuccess; ++k)
+        e = enqueue_generation(r->R, r->cap_stream, (adapt >> k) & 1u);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(r->cap_stream, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(r, e, "graph capture");
     }
+    if (e2 != hipSuccess) return fail(r, e2, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(r, e, "hipGraphInstantiate");
+    }
+    r->graphs.push_back({len, adapt, g, x});
+    *out = x;
+    return RVEA_OK;
+}
+
+// n generations from generation r->t + 1 as launches of up to kGraphGens
+// generations; a length that is a multiple of the adaptation period keeps
+// the adapting positions, and so the graph, the same from one launch to the
+// next.  launch = false only captures the graphs.
+rvea_status graph_launches(rvea_run r, int n, bool launch)
+{
+    const int64_t P = r->R.period;
+    const int L = P <= kGraphGens ? (int)(P * (kGraphGens / P)) : kGraphGens;
+    int64_t t = r->t;
+    for (int i = 0; i < n;) {
+        const int len = n - i < L ? n - i : L;
+        uint64_t adapt = 0;
+        for (int k = 0; k < len; ++k)
+            if ((t + 1 + k) % P == 0) adapt |= 1ull << k;
+        hipGraphExec_t x = nullptr;
+        rvea_status st = graph_for(r, len, adapt, &x);
+        if (st != RVEA_OK) return st;
+        if (launch) HIPCHK(r, hipGraphLaunch(x, r->stream));
+        t += len;
+        i += len;
+    }
+    if (launch) r->t = t;
     return RVEA_OK;
 }
 
 }  // namespace
+
+rvea_status rvea_prepare_generations(rvea_run r, int n)
+{
+    if (!r || n < 0) return RVEA_EINVAL;
+    if (n > 0 && (r->phase != 0 || r->batch)) return RVEA_ESTATE;
+    if (!r->use_graphs || n == 0) return RVEA_OK;
+    return graph_launches(r, n, false);
+}
 
 rvea_status rvea_run_generations(rvea_run r, int n)
 {
     if (!r || n < 0) return RVEA_EINVAL;
     if (n > 0 && (r->phase != 0 || r->batch)) return RVEA_ESTATE;
     if (r->use_graphs && r->timing == 0 && n > 0) {
-        rvea_status st = build_graphs(r);
+        rvea_status st = graph_launches(r, n, true);
         if (st != RVEA_OK) return st;
-        for (int i = 0; i < n; ++i) {
-            const bool adapt = (r->t + 1) % r->R.period == 0;
-            HIPCHK(r, hipGraphLaunch(r->gexec[adapt ? 1 : 0], r->stream));
-            r->t += 1;
-        }
         r->has_selection = true;
         return RVEA_OK;
     }
@@ -770,19 +836,6 @@ rvea_status rvea_kernel_time(rvea_run r, int kernel, double *ms, int64_t *launch
 
 rvea_status rvea_batch_retire(rvea_batch b, rvea_run r);
 
-namespace {
-
-void drop_graphs(rvea_run r)
-{
-    for (int v = 0; v < 2; ++v) {
-        if (r->gexec[v]) (void)hipGraphExecDestroy(r->gexec[v]);
-        if (r->graph[v]) (void)hipGraphDestroy(r->graph[v]);
-        r->gexec[v] = nullptr;
-        r->graph[v] = nullptr;
-    }
-}
-
-}  // namespace
 
 rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
 {

@@ -24,7 +24,8 @@ KERNEL_OFFSPRING, KERNEL_ASSOC, KERNEL_RERANK, KERNEL_GAMMA, KERNEL_ROLLOUT = 0,
 EXPORTS = [
     "rvea_default_params", "rvea_lattice_divisions", "rvea_footprint", "rvea_create",
     "rvea_create_policy",
-    "rvea_step", "rvea_select", "rvea_adapt", "rvea_run_generations", "rvea_set_graphs",
+    "rvea_step", "rvea_select", "rvea_adapt", "rvea_run_generations",
+    "rvea_prepare_generations", "rvea_set_graphs",
     "rvea_get_state",
     "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
     "rvea_get_counters",
@@ -80,6 +81,7 @@ def _load():
         "rvea_create_policy": [i64, i64, u64, P, P, P, sz, P, P],
         "rvea_step": [P], "rvea_select": [P], "rvea_adapt": [P],
         "rvea_run_generations": [P, i32],
+        "rvea_prepare_generations": [P, i32],
         "rvea_set_graphs": [P, i32],
         "rvea_get_state": [P, P, P, P, P, P, P, P],
         "rvea_set_state": [P, P, P, P, P, P, i64],
@@ -214,6 +216,10 @@ class Run:
 
     def run(self, n):
         self._chk(lib.rvea_run_generations(self._h, n), "rvea_run_generations")
+
+    def prepare(self, n):
+        """Capture the graphs run(n) would launch, without running them."""
+        self._chk(lib.rvea_prepare_generations(self._h, n), "rvea_prepare_generations")
 
     def set_graphs(self, on):
         self._chk(lib.rvea_set_graphs(self._h, 1 if on else 0), "rvea_set_graphs")

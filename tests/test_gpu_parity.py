@@ -377,3 +377,22 @@ def test_graph_replays_match_eager(P):
         b.synchronize()
     sa, sb = a.get_state(), b.get_state()
     assert np.array_equal(sa["X"], sb["X"]) and sa["t"] == sb["t"] == 29
+
+
+def test_multi_generation_graphs_match_eager(P):
+    """Graph launches of up to 16 generations, with the adaptation period
+    longer than a launch (20), so the adapting generation sits at different
+    positions of the captured runs, equal eager generations."""
+    prm = P.default_params(t_max=200)
+    a = P.Run(2, 3, 64, 120, 120, seed=5, params=prm)
+    b = P.Run(2, 3, 64, 120, 120, seed=5, params=prm)
+    a.set_graphs(False)
+    b.prepare(23)
+    for chunk in (23, 22, 16, 3):
+        a.run(chunk)
+        b.run(chunk)
+        sa, sb = a.get_state(), b.get_state()
+        for k in ("X", "F", "valid", "V", "gamma", "t"):
+            assert np.array_equal(sa[k], sb[k], equal_nan=True), (chunk, k)
+    assert sb["t"] == 64
+    assert not np.array_equal(sb["V"], b.get_state()["V0"])  # adapted
