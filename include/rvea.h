@@ -234,8 +234,9 @@ rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *laun
  * with the re-rank that reads their partials.  rvea_autotune draws the
  * next generation's offspring and ideal point without committing anything,
  * times every candidate on them with HIP events (best of three launches) and
- * keeps the fastest for the rest of the run (the adaptation's gamma pass
- * included).  Results do not depend on the choice: the association is
+ * keeps the fastest for the rest of the run.  The adaptation's gamma pass
+ * (its rows are the K vectors) gets its own rows per lane and chunk length,
+ * timed the same way on the current vectors.  Results do not depend on the choice: the association is
  * finished in binary64 over candidate tiles.  Needs the run between
  * generations, outside a batch and with timing off (RVEA_ESTATE); waits for
  * the stream; afterwards rvea_get_selection reports RVEA_ESTATE until the
@@ -249,6 +250,10 @@ typedef struct rvea_tuning {
     double default_us;          /* association + re-rank, default shape */
     double rerank_us;           /* best time of the chosen re-rank configuration */
     double rerank_default_us;   /* best time of the default one */
+    int32_t gamma_rows_per_lane;  /* gamma pass (rows = vectors): chosen rows per lane */
+    int32_t gamma_chunk_vectors;  /* gamma pass: chosen chunk length */
+    double gamma_us;              /* gamma pass (both passes), chosen shape */
+    double gamma_default_us;      /* gamma pass, default shape */
 } rvea_tuning;
 rvea_status rvea_autotune(rvea_run run, rvea_tuning *out);
 

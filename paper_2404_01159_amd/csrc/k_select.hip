@@ -659,13 +659,18 @@ hipError_t launch_rerank(const RunView &R, hipStream_t s)
     return hipGetLastError();
 }
 
-// gamma of Eq. 5 through the same two passes, rows = vectors
+// gamma of Eq. 5 through the same two passes, rows = vectors, with the
+// gamma pass's own chunking and rows per lane
 hipError_t launch_gamma(const RunView &R, hipStream_t s, int force)
 {
-    assoc_launch<true>(R, s, force);
+    RunView G = R;
+    G.KC = R.gKC;
+    G.CS = R.gCS;
+    G.rr = R.grr;
+    assoc_launch<true>(G, s, force);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    rerank_launch<true>(R, s, force);
+    rerank_launch<true>(G, s, force);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ struct RunView {
     int KC, CS;  // association: number of vector chunks and chunk length
     int rr;      // association: rows per lane (1, 2 or 4)
     int rk;      // re-rank: rows per wave (4, 8 or 16)
+    int gKC, gCS, grr;  // the same three for the gamma pass (rows = vectors)
 
     float *X;           // (K+N) x ld physical gene rows
     // The population after p generations lives in buffer p & 1 of each

@@ -336,6 +336,9 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.CS = L.CS;
     R.rr = 4;
     R.rk = default_rerank_rows(K + N);
+    R.gKC = L.KC;
+    R.gCS = L.CS;
+    R.grr = 4;
     char *w = (char *)workspace;
     R.X = (float *)(w + L.off[B_X]);
     R.slot_rows = (int32_t *)(w + L.off[B_SLOT]);
@@ -926,6 +929,46 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
         }
     }
     R.rk = rk_win;
+    // the gamma pass (rows = vectors, at adaptations): its own chunking and
+    // rows per lane, timed on the current vectors (it rewrites the same
+    // gamma every time)
+    const int grr0 = R.grr, gcs0 = R.gCS, gkc0 = R.gKC;
+    double g_def = -1.0, g_best = 1e30;
+    int g_rr = grr0, g_cs = gcs0;
+    int ncand = (int)cands.size() + 3;
+    for (int rr : {4, 2, 1}) {
+        for (int cs = CS0; cs <= 32 * kTile; cs *= 2) {
+            const int kc = (int)((R.K + cs - 1) / cs);
+            if (kc <= KC0) {
+                R.grr = rr;
+                R.gCS = cs;
+                R.gKC = kc;
+                HIPCHK(r, launch_gamma(R, r->stream, 1));  // warm
+                float best = 1e30f;
+                for (int rep_ = 0; rep_ < 3; ++rep_) {
+                    HIPCHK(r, hipEventRecord(a, r->stream));
+                    HIPCHK(r, launch_gamma(R, r->stream, 1));
+                    HIPCHK(r, hipEventRecord(b, r->stream));
+                    HIPCHK(r, hipEventSynchronize(b));
+                    float ms = 0.f;
+                    HIPCHK(r, hipEventElapsedTime(&ms, a, b));
+                    best = std::min(best, ms);
+                }
+                ++ncand;
+                if (rr == grr0 && cs == gcs0) g_def = best;
+                if (best < g_best) {
+                    g_best = best;
+                    g_rr = rr;
+                    g_cs = cs;
+                }
+            }
+            if ((int64_t)cs >= R.K) break;
+        }
+    }
+    R.grr = g_rr;
+    R.gCS = g_cs;
+    R.gKC = (int)((R.K + g_cs - 1) / g_cs);
+    (void)gkc0;
     r->pool.push_back(a);
     r->pool.push_back(b);
     HIPCHK(r, hipMemcpy(R.counters, saved, sizeof saved, hipMemcpyHostToDevice));
@@ -938,11 +981,15 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
         out->rows_per_lane = R.rr;
         out->chunk_vectors = R.CS;
         out->rerank_rows = R.rk;
-        out->candidates = (int32_t)cands.size() + 3;
+        out->candidates = ncand;
         out->assoc_us = win ? 1e3 * win->ms : -1.0;
         out->default_us = 1e3 * def_ms;
         out->rerank_us = 1e3 * rk_best;
         out->rerank_default_us = 1e3 * rk_def;
+        out->gamma_rows_per_lane = R.grr;
+        out->gamma_chunk_vectors = R.gCS;
+        out->gamma_us = 1e3 * g_best;
+        out->gamma_default_us = 1e3 * g_def;
     }
     return RVEA_OK;
 }

@@ -54,7 +54,9 @@ class Tuning(C.Structure):
     _fields_ = [("rows_per_lane", C.c_int32), ("chunk_vectors", C.c_int32),
                 ("rerank_rows", C.c_int32), ("candidates", C.c_int32), ("assoc_us", C.c_double),
                 ("default_us", C.c_double), ("rerank_us", C.c_double),
-                ("rerank_default_us", C.c_double)]
+                ("rerank_default_us", C.c_double), ("gamma_rows_per_lane", C.c_int32),
+                ("gamma_chunk_vectors", C.c_int32), ("gamma_us", C.c_double),
+                ("gamma_default_us", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -296,7 +298,10 @@ class Run:
         return dict(rows_per_lane=t.rows_per_lane, chunk_vectors=t.chunk_vectors,
                     rerank_rows=t.rerank_rows, candidates=t.candidates, assoc_us=t.assoc_us,
                     default_us=t.default_us, rerank_us=t.rerank_us,
-                    rerank_default_us=t.rerank_default_us)
+                    rerank_default_us=t.rerank_default_us,
+                    gamma_rows_per_lane=t.gamma_rows_per_lane,
+                    gamma_chunk_vectors=t.gamma_chunk_vectors, gamma_us=t.gamma_us,
+                    gamma_default_us=t.gamma_default_us)
 
     def kernel_time(self, kernel):
         ms = C.c_double(0)

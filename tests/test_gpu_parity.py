@@ -348,6 +348,8 @@ def test_autotuned_tiles_give_identical_runs(P, O, shape):
     assert t["rows_per_lane"] in (1, 2, 4) and t["chunk_vectors"] % 32 == 0
     assert t["candidates"] >= 6 and 0 < t["assoc_us"] <= t["default_us"]
     assert t["rerank_rows"] in (4, 8, 16) and 0 < t["rerank_us"] <= t["rerank_default_us"]
+    assert t["gamma_rows_per_lane"] in (1, 2, 4) and t["gamma_chunk_vectors"] % 32 == 0
+    assert 0 < t["gamma_us"] <= t["gamma_default_us"]
     a.run(12)
     b.run(12)
     sa, sb = a.get_state(), b.get_state()
