@@ -97,7 +97,7 @@ rvea_status rvea_footprint(int problem, int m, int d, int64_t N, int64_t K,
                            const rvea_params *params, size_t *bytes);
 
 /* Creates a run on the current HIP device and enqueues its initialization
- * (Alg. 2, line 3: N individuals uniform in [lb,ub]^d in slots 0..N-1, the
+ * (Alg. 2's initialization: N individuals uniform in [lb,ub]^d in slots 0..N-1, the
  * rest of the K slots empty; V = V_0; gamma of Eq. 5).
  *   workspace        device pointer, 256-byte aligned, >= footprint bytes
  *   hip_stream       hipStream_t (may be NULL)
@@ -139,17 +139,17 @@ rvea_status rvea_create_policy(int64_t N, int64_t K, uint64_t seed, const rvea_p
                                const rvea_lq_system *system, void *workspace,
                                size_t workspace_bytes, void *hip_stream, rvea_run *out);
 
-/* Alg. 2 line 5 and Appendix B for generation t = completed + 1: draws the
+/* Alg. 2's offspring step and Appendix B for generation t = completed + 1: draws the
  * N offspring by random mating, SBX and polynomial mutation from the
  * current population, and evaluates them (Eq. 1). */
 rvea_status rvea_step(rvea_run run);
 
-/* Alg. 2 lines 6-7 / Alg. 1: selects at most one survivor per reference
+/* Alg. 2's selection step / Alg. 1: selects at most one survivor per reference
  * vector from the K parent slots and the N offspring, writes the new
  * population into the slots and counts the generation as completed. */
 rvea_status rvea_select(rvea_run run);
 
-/* Alg. 2 line 8: when the completed generation count is a multiple of
+/* Alg. 2's update of V: when the completed generation count is a multiple of
  * ceil(fr * t_max), updates V from V_0 and the survivors' objective ranges
  * and recomputes gamma; otherwise does nothing. */
 rvea_status rvea_adapt(rvea_run run);

@@ -691,16 +691,16 @@ int ora_reproduce_pairs(const ora_params *P, uint64_t seed, int64_t t, int64_t N
 /* Selection (Alg. 1; Eq. 2, Eq. 4, Eq. 5).                                 */
 /* Merged population: rows 0..K-1 are the parent slots, K..K+N-1 the        */
 /* offspring; a row takes part iff mvalid[i] and all of F_i is finite.      */
-/*   z*_k  = min over taking-part rows of F_ik            (Alg. 1, line 3)  */
-/*   f'_i  = F_i - z*                                      (line 4)         */
-/*   A(i)  = argmax_j cos(f'_i, v_j), lowest j on ties     (line 5-6, Eq.2) */
+/*   z*_k  = min over taking-part rows of F_ik            (Alg. 1)         */
+/*   f'_i  = F_i - z*                                      (Alg. 1)         */
+/*   A(i)  = argmax_j cos(f'_i, v_j), lowest j on ties     (Alg. 1, Eq. 2)  */
 /*           (= argmin of the angle).  ||f'_i|| = 0 gives A(i) = 0,         */
 /*           theta = pi/2 and APD 0.                                        */
 /*   APD_i = (1 + m (t/t_max)^alpha theta_i / gamma_A(i)) ||f'_i||  (Eq. 4) */
 /*   surv(j) = argmin over {i : A(i) = j} of APD_i, lowest i on ties;       */
-/*             -1 when no row is associated with j (lines 14-15).           */
-/* Readings: t is the 1-based generation of this selection; the -1 mask of  */
-/* line 14 is the partition tensor's (an APD entry is never -1).           */
+/*             -1 when no row is associated with j (Alg. 1).                */
+/* Readings: t is the 1-based generation of this selection; Alg. 1's -1     */
+/* mask is the partition tensor's (an APD entry is never -1).              */
 /* ------------------------------------------------------------------------ */
 /* association, angle and APD of one objective row (Eq. 2, Eq. 4) */
 static void assoc_one(int m, int64_t K, const double *Fi, const double *zstar, const double *V,
@@ -877,7 +877,7 @@ int ora_generation(const ora_params *P, int problem, int m, int d, int64_t N, in
     if (parents_out) memcpy(parents_out, parents, sizeof(int32_t) * (size_t)(2 * Pp));
     if (surv_out) memcpy(surv_out, surv, sizeof(int32_t) * (size_t)K);
     {
-        /* new population: slot j <- merged row surv(j) (Alg. 1 line 16) */
+        /* new population: slot j <- merged row surv(j) (Alg. 1) */
         float *Xn = (float *)malloc(sizeof(float) * (size_t)(K * d));
         for (int64_t j = 0; j < K; ++j) {
             const int32_t s = surv[j];

@@ -1,4 +1,4 @@
-// k_gen.hip -- population-side kernels: initialization (Alg. 2 line 3),
+// k_gen.hip -- population-side kernels: initialization (Alg. 2),
 // per-generation bookkeeping of valid slots and free gene rows, and the
 // fused offspring kernel (random mating, SBX, polynomial mutation of
 // Appendix B, evaluation of Eq. 1).
@@ -65,10 +65,7 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
     const int32_t gen = (int32_t)(p + 1);
     const uint8_t *valid = valid_of(R, p);
     const float *Fm = fm_of(R, p);
-    if (j < R.K) {
-        R.key[j] = ~0ull;
-        R.surv[j] = 0x7fffffff;
-    }
+    if (j < R.K) R.key[j] = ~0ull;
     if (j < R.m) {
         R.rbits[j] = 0xffffffffu;  // survivors' minimum
         R.rbits[R.m + j] = 0u;     // survivors' maximum

@@ -2,9 +2,9 @@
 //
 // The paper forms the n x r angle tensor, masks it per column and takes
 // column-wise APD argmins.  Here the 2N x K cosine matrix is never stored:
-// (z*, the column minima over the rows that take part (Alg. 1 l.3), is
-// reduced where the rows are produced: parents in k_prep_count, children in
-// k_offspring or k_rollout.)
+// (z*, the column minima over the rows that take part (Alg. 1), is reduced
+// where the rows are produced: parents in k_prep, children in k_offspring
+// or k_rollout.)
 //   k_assoc   single-precision pass over (row, vector) pairs: V tiles of 32
 //             vectors sit in LDS and are broadcast to every lane; each lane
 //             holds RR rows of f' = F - z* and keeps, per vector chunk, the
@@ -14,9 +14,10 @@
 //   k_rerank  double precision over the candidate tiles only: cosine
 //             f'.v / (|f'| |v|) written as an fma chain, argmax with lowest
 //             index on ties (Eq. 2), theta = acos, APD of Eq. 4 with the
-//             vector's gamma (Eq. 5); per-vector minimum APD by 64-bit atomic
-//             min on the (non-negative) double's bit pattern
-//   k_surv    the lowest row index attaining that minimum (Alg. 1 l.15)
+//             vector's gamma (Eq. 5); per vector the minimum of (APD, row)
+//             by one 64-bit atomic min on a packed word (the APD's bit
+//             pattern above the row index), so the survivor (Alg. 1's
+//             per-vector argmin, lowest row on ties) needs no second pass
 //   k_newpop  slot j <- its survivor's gene row and objectives, written into
 //             the other buffer of the population pair (no copy-back); also
 //             the next generation's row stamps, block counts and resets
@@ -459,7 +460,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     if (!GAMMA && st == 2) {
         R.assoc[row_i] = 0;
         R.apd[row_i] = 0.0;
-        atomicMin(&R.key[0], 0ull);
+        atomicMin(&R.key[0], (unsigned long long)row_i);  // APD 0
         return;
     }
     double best = s_rb[t];
@@ -475,33 +476,26 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     const double a = (1.0 + *R.pen * th / R.gamma[bj]) * nrm;
     R.assoc[row_i] = (int32_t)bj;
     R.apd[row_i] = a;
-    atomicMin(&R.key[bj], (unsigned long long)__double_as_longlong(a));
+    // (APD, row) in one word: the APD's bit pattern (monotone for doubles
+    // >= 0) above the row index, its lowest kb bits dropped; the minimum
+    // names the survivor directly, the lowest row among equal APDs
+    const unsigned long long ab = (unsigned long long)__double_as_longlong(a);
+    atomicMin(&R.key[bj], ((ab >> R.kb) << R.kb) | (unsigned long long)row_i);
 }
 
-// k_surv also counts the generation: from here on t_done is the new
-// population's index (no other workgroup of this kernel reads it)
-__device__ __forceinline__ void surv_body(const RunView &R, int64_t bx)
-{
-    const int64_t i = bx * 256 + threadIdx.x;
-    if (bx == 0 && threadIdx.x == 0) *R.t_done += 1;
-    if (i >= R.M) return;
-    const int32_t j = R.assoc[i];
-    if (j < 0) return;
-    if ((unsigned long long)__double_as_longlong(R.apd[i]) == R.key[j])
-        atomicMin(&R.surv[j], (int32_t)i);
-}
-
-// The new population g (Alg. 1, last line) written into the other buffer of
-// each pair: slot j <- its survivor's gene row and objectives, or empty.  The
-// same pass stamps the rows generation g+1 will read, counts valid slots per
-// block (the next preparation's offsets), reduces the survivors' extremes
-// for a possible adaptation, and clears generation g+1's ideal point and
-// free-row counter.
+// The new population g (Alg. 1) written into the other buffer of
+// each pair: slot j <- its survivor's gene row and objectives, or empty; the
+// survivor is the row index held in the vector's key.  The same pass stamps
+// the rows generation g+1 will read, counts valid slots per block (the next
+// preparation's offsets), reduces the survivors' extremes for a possible
+// adaptation, and clears generation g+1's ideal point and free-row counter.
+// The last workgroup to finish counts the generation (t_done = g): every
+// workgroup has read t_done before it reports.
 __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
 {
     __shared__ uint32_t smin[kMaxM], smax[kMaxM];
     __shared__ int wc[4];
-    const int64_t g = *R.t_done;  // counted by k_surv
+    const int64_t g = *R.t_done + 1;
     if (threadIdx.x < kMaxM) {
         smin[threadIdx.x] = 0xffffffffu;
         smax[threadIdx.x] = 0u;
@@ -518,12 +512,14 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
     int v = 0;
     int32_t s = 0;
     if (j < R.K) {
-        s = R.surv[j];
-        if (s == 0x7fffffff) {
+        const unsigned long long kj = R.key[j];
+        if (kj == ~0ull) {  // no row associated with vector j
             R.surv[j] = -1;
             val1[j] = 0;
             row1[j] = row0[j];
         } else {
+            s = (int32_t)(kj & ((1ull << R.kb) - 1));
+            R.surv[j] = s;
             v = 1;
             const int32_t row = s < R.K ? row0[s] : R.off_row[s - R.K];
             val1[j] = 1;
@@ -552,7 +548,15 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
         if (smin[threadIdx.x] != 0xffffffffu) atomicMin(&R.rbits[threadIdx.x], smin[threadIdx.x]);
         atomicMax(&R.rbits[R.m + threadIdx.x], smax[threadIdx.x]);
     }
-    if (threadIdx.x == 0) R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
+    if (threadIdx.x == 0) {
+        R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
+        __threadfence();
+        const uint32_t nb = (uint32_t)((R.K + 255) / 256);
+        if (atomicAdd(R.ndone, 1u) == nb - 1) {
+            *R.t_done = g;
+            *R.ndone = 0;
+        }
+    }
 }
 
 // ------------------------------------------------------- single-run kernels
@@ -566,7 +570,6 @@ __global__ __launch_bounds__(64) void k_rerank(RunView R, int gate)
 {
     rerank_body<MD, GAMMA, ROWS>(R, blockIdx.x, gate);
 }
-__global__ __launch_bounds__(256) void k_surv(RunView R) { surv_body(R, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_newpop(RunView R) { newpop_body(R, blockIdx.x); }
 
 // ----------------------------------------------------- batched (many runs)
@@ -585,11 +588,6 @@ __global__ __launch_bounds__(64) void kb_rerank(const RunView *runs, const Span 
 {
     const int s = find_span(sp, n, blockIdx.x);
     rerank_body<MD, GAMMA, kBatchRows>(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
-}
-__global__ __launch_bounds__(256) void kb_surv(const RunView *runs, const Span *sp, int n)
-{
-    const int s = find_span(sp, n, blockIdx.x);
-    surv_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 __global__ __launch_bounds__(256) void kb_newpop(const RunView *runs, const Span *sp, int n)
 {
@@ -676,7 +674,6 @@ hipError_t launch_gamma(const RunView &R, hipStream_t s, int force)
 
 hipError_t launch_select_back(const RunView &R, hipStream_t s)
 {
-    k_surv<<<blocks(R.M, 256), 256, 0, s>>>(R);
     k_newpop<<<blocks(R.K, 256), 256, 0, s>>>(R);
     return hipGetLastError();
 }
@@ -696,7 +693,6 @@ hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Sp
     constexpr int RR = 4;
     const dim3 g((unsigned)blocks);
     switch (phase) {
-    case BP_SURV: kb_surv<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_NEWPOP: kb_newpop<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_ASSOC:
 #define RVEA_BA(MV) kb_assoc<MV, RR, false><<<g, 256, 0, s>>>(runs, sp, n)

@@ -4,7 +4,7 @@
 //               of {1..H+m-1} in lexicographic order (parts a_i = c_i -
 //               c_{i-1} - 1, w = a/H), normalised to unit length
 //   (gamma of Eq. 5 runs through the association kernels, k_select.hip)
-//   k_adapt_v   Alg. 2 line 8 (rule of the cited RVEA): V_j = V0_j o r /
+//   k_adapt_v   Alg. 2's update of V (rule of the cited RVEA): V_j = V0_j o r /
 //               |V0_j o r| with r the survivors' per-objective range; left
 //               unchanged if some range is not positive and finite
 //   k_vec_aux   float copy of V (padded rows) and row norms
@@ -158,7 +158,6 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
         const int S = pick_segment(R.d);
         return ((R.N + 1) / 2 + (kBlock / S) - 1) / (kBlock / S);
     }
-    case BP_SURV: return (R.M + 255) / 256;
     case BP_ASSOC:
     case BP_GAMMA_ASSOC: return batch_phase_nbx(phase, R) * R.KC;
     case BP_RERANK: return (R.M + rerank_rows_per_wave() - 1) / rerank_rows_per_wave();

@@ -62,9 +62,11 @@ struct RunView {
     uint32_t *pmask;    // KC x M candidate-tile masks
     int32_t *assoc;     // M
     double *apd;        // M
-    unsigned long long *key;  // K
-    int32_t *surv;      // K
+    unsigned long long *key;  // K: min over associated rows of (APD, row), packed
+    int kb;             // row-index bits of a key: M < 2^kb
+    int32_t *surv;      // K: survivor's merged row of the last selection, or -1
     int64_t *t_done;    // completed generations
+    uint32_t *ndone;    // 1: k_newpop workgroups finished (the last one counts the generation)
     unsigned long long *counters;  // 0 non-finite rows, 1 full rescans, 2 site overflow
     int32_t *vchanged;  // 1: adaptation changed V
     double *pen;        // 1: m (t/t_max)^alpha of the current generation

@@ -32,7 +32,7 @@ enum Buf {
     B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_MVALID, B_PARENTS, B_VS,
     B_NVALID, B_STAMP, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
     B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_BCOUNT, B_FREECNT, B_PEN,
-    B_LQ, B_COUNT
+    B_NDONE, B_LQ, B_COUNT
 };
 
 int64_t binomial(int64_t n, int64_t k)
@@ -97,7 +97,7 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
         (size_t)K * m * 8, (size_t)K * L.stride * 4, (size_t)K * 8, (size_t)K * 8,
         (size_t)2 * m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
         (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4,
-        (size_t)((K + N + 255) / 256) * 4, 4, 8,
+        (size_t)((K + N + 255) / 256) * 4, 4, 8, 4,
         problem == kPolicy ? (size_t)kLqFloats * 4 : 0};
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
@@ -366,6 +366,9 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.apd = (double *)(w + L.off[B_APD]);
     R.key = (unsigned long long *)(w + L.off[B_KEY]);
     R.surv = (int32_t *)(w + L.off[B_SURV]);
+    R.kb = 1;
+    while (((int64_t)1 << R.kb) <= R.M) ++R.kb;  // row indices below 2^kb
+    R.ndone = (uint32_t *)(w + L.off[B_NDONE]);
     R.t_done = (int64_t *)(w + L.off[B_TDONE]);
     R.counters = (unsigned long long *)(w + L.off[B_COUNTERS]);
     R.vchanged = (int32_t *)(w + L.off[B_VCHANGED]);
@@ -389,6 +392,7 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     if (e == hipSuccess)
         e = hipMemsetAsync(R.counters, 0, 3 * sizeof(unsigned long long), r->stream);
     if (e == hipSuccess) e = hipMemsetAsync(R.vchanged, 0, 4, r->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(R.ndone, 0, 4, r->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(R.stamp, 0xff, (size_t)(K + N) * 4, r->stream);
     if (e == hipSuccess) e = launch_lattice(R, r->stream, r->H);

@@ -35,7 +35,7 @@ hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring);
 // span table (runs of the same template class: segment width for the
 // offspring, objective count for the association phases).
 enum BatchPhase {
-    BP_PREP, BP_OFFSPRING, BP_ASSOC, BP_RERANK, BP_SURV,
+    BP_PREP, BP_OFFSPRING, BP_ASSOC, BP_RERANK,
     BP_NEWPOP, BP_ADAPT, BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
 int batch_phase_class(int phase, const RunView &R);       // template class of a run

@@ -63,7 +63,7 @@ def lockstep(P, O, run, prm, gens, stats):
         run.adapt()
         st2 = run.get_state()
         assert st2["t"] == t
-        # the new population is the survivors' rows (Alg. 1 line 16)
+        # the new population is the survivors' rows (Alg. 1)
         Xm = np.vstack([st["X"], off["X"]])
         s = sel["surv"]
         assert np.array_equal(st2["valid"], (s >= 0).astype(np.uint8))
