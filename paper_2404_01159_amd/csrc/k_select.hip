@@ -218,6 +218,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     __shared__ int s_cnt[kRows], s_off[kRows];
     __shared__ int s_item[kWaveItems];  // row << 27 | first vector of the tile
     __shared__ double s_best[kWaveItems];
+    __shared__ double s_gam[kWaveItems];  // gamma of the item's best vector (selection)
     __shared__ int s_bj[kWaveItems];
     __shared__ unsigned char s_dup[kWaveItems];
 
@@ -231,6 +232,20 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     int state = 0, cnt = 0;
     float thr = 0.f;
     const bool act = i < nrows && (GAMMA || R.mvalid[i]);
+    // this lane's chunk maxima and tile masks, the first kCache chunks read
+    // together (one round trip; they do not depend on the row's objectives)
+    float cmax[kCache];
+    uint32_t cmask[kCache];
+#pragma unroll
+    for (int u = 0; u < kCache; ++u) {
+        const int c = sub + u * kLanes;
+        cmax[u] = -INFINITY;
+        cmask[u] = 0u;
+        if (act && c < R.KC) {
+            cmax[u] = R.pmax[(int64_t)c * R.M + i];
+            cmask[u] = R.pmask[(int64_t)c * R.M + i];
+        }
+    }
     if (act) {
         double f[MD], nrm;
         float n2f = 0.f;
@@ -262,9 +277,9 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
             s_nrm[r] = nrm;
         }
         state = (!GAMMA && nrm == 0.0) ? 2 : 1;
-        float gm = -INFINITY;
-#pragma unroll 8
-        for (int c = sub; c < R.KC; c += kLanes) gm = fmaxf(gm, R.pmax[(int64_t)c * R.M + i]);
+        float gm = fmaxf(fmaxf(cmax[0], cmax[1]), fmaxf(cmax[2], cmax[3]));
+        for (int c = sub + kCache * kLanes; c < R.KC; c += kLanes)
+            gm = fmaxf(gm, R.pmax[(int64_t)c * R.M + i]);
         thr = gm;
         if (!GAMMA) thr = gm - two_eps(sqrtf(n2f));
     }
@@ -272,20 +287,17 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
 #pragma unroll
     for (int o = 1; o < kLanes; o <<= 1) thr = fmaxf(thr, __shfl_xor(thr, o, 64));
     if (GAMMA && act && thr > -INFINITY) thr -= two_eps_dist(-thr);  // scores are -|v_i - v_j|^2
-    // candidate tiles of this lane's chunks (the first kCache chunks kept)
-    int mine = 0, mc[kCache];
-    uint32_t mm[kCache];
+    // candidate tiles of this lane's chunks: those in registers, then any
+    // further chunks (more than kCache per lane) read again
+    bool more = false;
     if (act && state == 1) {
-#pragma unroll 4
-        for (int c = sub; c < R.KC; c += kLanes) {
+#pragma unroll
+        for (int u = 0; u < kCache; ++u)
+            if (cmax[u] >= thr) cnt += __popc(cmask[u]);
+        for (int c = sub + kCache * kLanes; c < R.KC; c += kLanes) {
             if (R.pmax[(int64_t)c * R.M + i] >= thr) {
-                const uint32_t mk = R.pmask[(int64_t)c * R.M + i];
-                if (mine < kCache) {
-                    mc[mine] = c;
-                    mm[mine] = mk;
-                }
-                ++mine;
-                cnt += __popc(mk);
+                more = true;
+                cnt += __popc(R.pmask[(int64_t)c * R.M + i]);
             }
         }
     }
@@ -328,10 +340,11 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
                 s_item[q++] = (r << 27) | (int)((int64_t)c * R.CS + (int64_t)tl * kTile);
             }
         };
-        if (mine <= kCache) {
-            for (int u = 0; u < mine; ++u) put(mc[u], mm[u]);
-        } else {  // more chunks than cached: scan them again
-            for (int c = sub; c < R.KC; c += kLanes)
+#pragma unroll
+        for (int u = 0; u < kCache; ++u)
+            if (cmax[u] >= thr) put(sub + u * kLanes, cmask[u]);
+        if (more) {
+            for (int c = sub + kCache * kLanes; c < R.KC; c += kLanes)
                 if (R.pmax[(int64_t)c * R.M + i] >= thr) put(c, R.pmask[(int64_t)c * R.M + i]);
         }
     }
@@ -342,7 +355,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     for (int k = 0; k < rounds; ++k) {
         const int e = t + 64 * k;
         const int item = e >> 5;
-        double best = -INFINITY;
+        double best = -INFINITY, gam = 0.0;
         int64_t bj = R.K;
         int dup = 0;
         if (item < total) {
@@ -353,6 +366,8 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
                 double f[MD];
 #pragma unroll
                 for (int kk = 0; kk < MD; ++kk) f[kk] = s_f[row][kk];
+                // the vector's gamma comes in the same round trip as V and |v|
+                if (!GAMMA) gam = R.gamma[j];
                 const double cv = dotd<MD>(f, R.V + j * MD) / (s_nrm[row] * R.vn[j]);
                 if (GAMMA && cv >= 1.0) {
                     dup = 1;
@@ -366,14 +381,18 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         for (int o = 16; o > 0; o >>= 1) {
             const double ob = __shfl_xor(best, o, 32);
             const int64_t oj = __shfl_xor(bj, o, 32);
+            double og = 0.0;
+            if (!GAMMA) og = __shfl_xor(gam, o, 32);
             dup |= __shfl_xor(dup, o, 32);
             if (ob > best || (ob == best && oj < bj)) {
                 best = ob;
                 bj = oj;
+                gam = og;
             }
         }
         if ((t & 31) == 0 && item < total) {
             s_best[item] = best;
+            s_gam[item] = gam;
             s_bj[item] = (int)bj;
             s_dup[item] = dup;
         }
@@ -381,11 +400,11 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     __syncthreads();
 
     // ---- phase 3: one lane per row merges its items
-    __shared__ double s_rb[kRows];
+    __shared__ double s_rb[kRows], s_rg[kRows];
     __shared__ int s_rj[kRows], s_full[kRows];
     if (t < kRows) {
         const int st = s_state[t];
-        double best = -INFINITY;
+        double best = -INFINITY, gam = 0.0;
         int64_t bj = R.K;
         bool full = st == 3;
         if (st == 1) {
@@ -397,12 +416,14 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
                 if (j < R.K && (b > best || (b == best && j < bj))) {
                     best = b;
                     bj = j;
+                    gam = s_gam[q];
                 }
             }
             if (bj >= R.K) full = true;
         }
         s_full[t] = full ? 1 : 0;
         s_rb[t] = best;
+        s_rg[t] = gam;
         s_rj[t] = (int)bj;
     }
     __syncthreads();
@@ -442,6 +463,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
             atomicAdd(&R.counters[1], 1ull);
             s_rb[rr] = best;
             s_rj[rr] = (int)bj;
+            if (!GAMMA) s_rg[rr] = bj < R.K ? R.gamma[bj] : R.gamma[0];
         }
     }
     __syncthreads();
@@ -469,11 +491,13 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         R.gamma[row_i] = bj < R.K ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
         return;
     }
-    if (bj >= R.K) bj = 0;  // no finite cosine (cannot happen for a finite, nonzero row)
+    // no finite cosine (cannot happen for a finite, nonzero row): vector 0
+    const double gj = bj < R.K ? s_rg[t] : R.gamma[0];
+    if (bj >= R.K) bj = 0;
     const double nrm = s_nrm[t];
     const double cc = best > 1.0 ? 1.0 : (best < -1.0 ? -1.0 : best);
     const double th = acos(cc);
-    const double a = (1.0 + *R.pen * th / R.gamma[bj]) * nrm;
+    const double a = (1.0 + *R.pen * th / gj) * nrm;
     R.assoc[row_i] = (int32_t)bj;
     R.apd[row_i] = a;
     // (APD, row) in one word: the APD's bit pattern (monotone for doubles
