@@ -574,7 +574,9 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
     }
     if (threadIdx.x == 0) {
         R.bcount[bx] = wc[0] + wc[1] + wc[2] + wc[3];
-        __threadfence();
+        // no fence: the last workgroup only writes t_done, and every
+        // workgroup's read of it completed (its value was used by all waves
+        // before the barrier above) before its own count was added
         const uint32_t nb = (uint32_t)((R.K + 255) / 256);
         if (atomicAdd(R.ndone, 1u) == nb - 1) {
             *R.t_done = g;
