@@ -40,12 +40,22 @@ __global__ void k_lattice(RunView R, int H)
     int64_t prev = 0;
     double w[kMaxM];
     for (int i = 0; i < kk; ++i) {
-        int64_t v = prev + 1;
-        for (;; ++v) {
-            const uint64_t cnt = binom(n - v, kk - 1 - i);
-            if ((uint64_t)x < cnt) break;
-            x -= (int64_t)cnt;
+        // subsets whose next element lies in [prev+1, v]: by the hockey-stick
+        // identity C(n-prev, r+1) - C(n-v, r+1); the next element is the
+        // smallest v whose count exceeds x (binary search, O(log H) counts)
+        const int r = kk - 1 - i;
+        const uint64_t all = binom(n - prev, r + 1);
+        const uint64_t T = all - (uint64_t)x;
+        int64_t lo = prev + 1, hi = n - r;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (binom(n - mid, r + 1) < T)
+                hi = mid;
+            else
+                lo = mid + 1;
         }
+        const int64_t v = lo;
+        x -= (int64_t)(all - binom(n - v + 1, r + 1));
         w[i] = (double)(v - prev - 1) / (double)H;
         prev = v;
     }
