@@ -639,6 +639,22 @@ int pick_segment(int d)
     return S;
 }
 
+// The offspring kernel runs 4 wavefronts per SIMD (its register use), so
+// 256 CUs hold 4,096 at once.  With one pair per 64-lane segment, 4,097 to
+// 8,192 pairs would need a second, mostly idle round of wavefronts; 32-lane
+// segments (two pairs per wavefront, twice the quads per lane) fit them in
+// one.  A fixed constant, not the device's count, so that results (the
+// order of the distance sums) do not depend on the device.
+constexpr int64_t kResidentOffspringWaves = 4096;
+
+int offspring_segment(int d, int64_t N)
+{
+    const int S = pick_segment(d);
+    const int64_t P = (N + 1) / 2;
+    if (S == 64 && P > kResidentOffspringWaves && P <= 2 * kResidentOffspringWaves) return 32;
+    return S;
+}
+
 #define RVEA_SEG_DISPATCH(S, KERNEL, GRID_UNITS, STREAM, VIEW)                                 \
     do {                                                                                     \
         const int64_t units_ = (GRID_UNITS);                                                 \
@@ -710,7 +726,7 @@ hipError_t launch_prepare(const RunView &R, hipStream_t s)
 template <int NR, int DK>
 void launch_offspring_as(const RunView &R, hipStream_t s)
 {
-    const int S = pick_segment(R.d);
+    const int S = offspring_segment(R.d, R.N);
     const int64_t P = (R.N + 1) / 2;
     switch (S) {
     case 4: k_offspring<4, NR, DK><<<dim3((unsigned)((P + 63) / 64)), kBlock, 0, s>>>(R); break;

@@ -147,7 +147,7 @@ hipError_t launch_batch_vectors(int phase, int cls, const RunView *runs, const S
 // block counts and template classes of the batched phases
 int batch_phase_class(int phase, const RunView &R)
 {
-    if (phase == BP_OFFSPRING) return pick_segment(R.d);
+    if (phase == BP_OFFSPRING) return offspring_segment(R.d, R.N);
     if (phase == BP_ASSOC || phase == BP_RERANK || phase == BP_GAMMA_ASSOC ||
         phase == BP_GAMMA_RERANK)
         return R.m;
@@ -165,7 +165,7 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
     switch (phase) {
     case BP_PREP: return (R.K + R.N + 255) / 256;
     case BP_OFFSPRING: {
-        const int S = pick_segment(R.d);
+        const int S = offspring_segment(R.d, R.N);
         return ((R.N + 1) / 2 + (kBlock / S) - 1) / (kBlock / S);
     }
     case BP_ASSOC:

@@ -9,7 +9,8 @@
 
 namespace rvea {
 
-int pick_segment(int d);
+int pick_segment(int d);                 // lanes per individual (initialization)
+int offspring_segment(int d, int64_t N);  // lanes per parent pair
 int assoc_rows_per_block();
 int rerank_rows_per_wave();      // batched launch
 int default_rerank_rows(int64_t rows);  // single-run default for this many rows
