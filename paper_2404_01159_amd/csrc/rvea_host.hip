@@ -844,6 +844,41 @@ rvea_status rvea_kernel_time(rvea_run r, int kernel, double *ms, int64_t *launch
 rvea_status rvea_batch_retire(rvea_batch b, rvea_run r);
 
 
+}  // extern "C"
+
+namespace {
+
+// Chunk lengths to try for `rows` rows against K vectors at rr rows per
+// lane: the default length times powers of two, and the lengths that make
+// the workgroup count (row blocks x chunks) just below k times the CU count,
+// k = 1..8, so that no CU runs one more workgroup than the others (each the
+// shortest multiple of the tile with its chunk count).  At most KC0 chunks;
+// the default length comes first.
+std::vector<int> chunk_candidates(int64_t rows, int64_t K, int rr, int CS0, int KC0, int cus)
+{
+    std::vector<int> out;
+    auto add = [&](int64_t cs) {
+        if (cs < CS0 || cs > 32 * kTile || (K + cs - 1) / cs > KC0) return;
+        for (int c : out)
+            if (c == cs) return;
+        out.push_back((int)cs);
+    };
+    for (int64_t cs = CS0;; cs *= 2) {
+        add(cs);
+        if (cs >= K || cs >= 32 * kTile) break;
+    }
+    const int64_t nbi = (rows + 256 * rr - 1) / (256 * rr);
+    for (int k = 1; k <= 8; ++k) {
+        const int64_t kc = (int64_t)k * cus / nbi;
+        if (kc >= 1) add(((K + kc - 1) / kc + kTile - 1) / kTile * kTile);
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
 rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
 {
     if (!r) return RVEA_EINVAL;
@@ -864,12 +899,11 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
         int rr, cs;
         float ms;  // association + re-rank
     };
+    int cus = 0;
+    HIPCHK(r, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device));
     std::vector<Cand> cands;
     for (int rr : {4, 2, 1})
-        for (int cs = CS0; cs <= 32 * kTile; cs *= 2) {
-            cands.push_back({rr, cs, 0.f});
-            if ((int64_t)cs >= R.K) break;
-        }
+        for (int cs : chunk_candidates(R.M, R.K, rr, CS0, KC0, cus)) cands.push_back({rr, cs, 0.f});
     const int saved_rr = R.rr, saved_cs = R.CS, saved_kc = R.KC;
     double def_ms = -1.0;
     for (auto &c : cands) {
@@ -941,9 +975,9 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     int g_rr = grr0, g_cs = gcs0;
     int ncand = (int)cands.size() + 3;
     for (int rr : {4, 2, 1}) {
-        for (int cs = CS0; cs <= 32 * kTile; cs *= 2) {
+        for (int cs : chunk_candidates(R.K, R.K, rr, CS0, KC0, cus)) {
             const int kc = (int)((R.K + cs - 1) / cs);
-            if (kc <= KC0) {
+            {  // timed as one launch of both passes
                 R.grr = rr;
                 R.gCS = cs;
                 R.gKC = kc;
@@ -966,7 +1000,6 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
                     g_cs = cs;
                 }
             }
-            if ((int64_t)cs >= R.K) break;
         }
     }
     R.grr = g_rr;
