@@ -397,10 +397,10 @@ __device__ __forceinline__ float dterm(int problem, float z)
 // and DK = -1 reads problem and indices from the run (the batched kernel).
 // Every variant takes the same arithmetic steps, so results do not depend on
 // which one ran.
-template <int S, int NR, int DK>
+template <int S, int NR, int DK, int BS>
 __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
 {
-    constexpr int SEGS = kBlock / S;
+    constexpr int SEGS = BS / S;
     __shared__ int32_t sh_sites[SEGS][2][kMaxSites];
     __shared__ double sh_mags[SEGS][2][kMaxSites];
     __shared__ uint32_t szmin[kMaxM];
@@ -611,10 +611,15 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     }
 }
 
+// Workgroups of one wavefront: the pairs spread over the CUs in the finest
+// steps (the kernel's few wavefronts per SIMD make whole-workgroup
+// granularity visible as idle SIMDs).
+constexpr int kOffBlock = 64;
+
 template <int S, int NR, int DK>
-__global__ __launch_bounds__(kBlock) void k_offspring(RunView R)
+__global__ __launch_bounds__(kOffBlock) void k_offspring(RunView R)
 {
-    offspring_body<S, NR, DK>(R, blockIdx.x);
+    offspring_body<S, NR, DK, kOffBlock>(R, blockIdx.x);
 }
 
 // ----------------------------------------------------- batched (many runs)
@@ -627,7 +632,7 @@ template <int S>
 __global__ __launch_bounds__(kBlock) void kb_offspring(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
-    offspring_body<S, 0, -1>(runs[sp[s].run], blockIdx.x - sp[s].start);
+    offspring_body<S, 0, -1, kBlock>(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 
 // ------------------------------------------------------------- launchers
@@ -723,17 +728,19 @@ hipError_t launch_prepare(const RunView &R, hipStream_t s)
     return hipGetLastError();
 }
 
+static dim3 blocks_of(int64_t units, int per) { return dim3((unsigned)((units + per - 1) / per)); }
+
 template <int NR, int DK>
 void launch_offspring_as(const RunView &R, hipStream_t s)
 {
     const int S = offspring_segment(R.d, R.N);
     const int64_t P = (R.N + 1) / 2;
     switch (S) {
-    case 4: k_offspring<4, NR, DK><<<dim3((unsigned)((P + 63) / 64)), kBlock, 0, s>>>(R); break;
-    case 8: k_offspring<8, NR, DK><<<dim3((unsigned)((P + 31) / 32)), kBlock, 0, s>>>(R); break;
-    case 16: k_offspring<16, NR, DK><<<dim3((unsigned)((P + 15) / 16)), kBlock, 0, s>>>(R); break;
-    case 32: k_offspring<32, NR, DK><<<dim3((unsigned)((P + 7) / 8)), kBlock, 0, s>>>(R); break;
-    default: k_offspring<64, NR, DK><<<dim3((unsigned)((P + 3) / 4)), kBlock, 0, s>>>(R); break;
+    case 4: k_offspring<4, NR, DK><<<blocks_of(P, kOffBlock / 4), kOffBlock, 0, s>>>(R); break;
+    case 8: k_offspring<8, NR, DK><<<blocks_of(P, kOffBlock / 8), kOffBlock, 0, s>>>(R); break;
+    case 16: k_offspring<16, NR, DK><<<blocks_of(P, kOffBlock / 16), kOffBlock, 0, s>>>(R); break;
+    case 32: k_offspring<32, NR, DK><<<blocks_of(P, kOffBlock / 32), kOffBlock, 0, s>>>(R); break;
+    default: k_offspring<64, NR, DK><<<blocks_of(P, kOffBlock / 64), kOffBlock, 0, s>>>(R); break;
     }
 }
 
