@@ -537,12 +537,13 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
     int32_t s = 0;
     if (j < R.K) {
         const unsigned long long kj = R.key[j];
-        if (kj == ~0ull) {  // no row associated with vector j
+        const int64_t si = (int64_t)(kj & ((1ull << R.kb) - 1));
+        if (kj == ~0ull || si >= R.M) {  // no row associated with vector j
             R.surv[j] = -1;
             val1[j] = 0;
             row1[j] = row0[j];
         } else {
-            s = (int32_t)(kj & ((1ull << R.kb) - 1));
+            s = (int32_t)si;
             R.surv[j] = s;
             v = 1;
             const int32_t row = s < R.K ? row0[s] : R.off_row[s - R.K];
