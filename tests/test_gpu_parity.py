@@ -162,6 +162,22 @@ def test_arbitrary_state_and_parameters(P, O):
     run.close()
 
 
+@pytest.mark.parametrize("case", [
+    # problem, m, d, N, K: the smallest lattices, a single child, odd N
+    (2, 2, 2, 1, 2),
+    (1, 3, 3, 1, 3),
+    (3, 2, 5, 3, 4),
+    (1, 4, 4, 2, 4),
+])
+def test_tiny_runs_match_oracle(P, O, case):
+    problem, m, d, N, K = case
+    prm = P.default_params(t_max=12)
+    run = P.Run(problem, m, d, N, K, seed=17, params=prm)
+    stats = lockstep(P, O, run, prm, 12, new_stats())
+    assert stats["straddles"] <= 2 and stats["near_ties"] <= 1, stats
+    run.close()
+
+
 def test_nonfinite_rows_are_dropped(P, O):
     problem, m, d, N, K = 2, 3, 12, 105, 105
     run = P.Run(problem, m, d, N, K, seed=4)
