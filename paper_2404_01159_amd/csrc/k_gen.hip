@@ -96,7 +96,8 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
     }
     int tot;
     const int pos = block_scan_256(v, &tot);
-    if (v) R.vs[offset + pos] = (int32_t)j;
+    if (v)  // the slot and its row: a parent's genes are one lookup away
+        reinterpret_cast<int2 *>(R.vs)[offset + pos] = make_int2((int32_t)j, slot_row_of(R, p)[j]);
     const int64_t nblk = (R.K + 255) / 256;
     if (bx == nblk - 1 && threadIdx.x == 0) *R.nvalid = offset + tot;
     if (threadIdx.x < R.m && zmin[threadIdx.x] != 0xffffffffu)
@@ -430,11 +431,15 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     }
 
     // random mating: two uniform draws over the valid slots
-    int32_t a = 0, b = 0;
+    int32_t a = 0, b = 0, rowa = 0, rowb = 0;
     if (active) {
         const W4 w = draw(R, 0u, (uint32_t)p, t, TAG_MATE);
-        a = R.vs[below(w.w[0], nv)];
-        b = R.vs[below(w.w[1], nv)];
+        const int2 ea = reinterpret_cast<const int2 *>(R.vs)[below(w.w[0], nv)];
+        const int2 eb = reinterpret_cast<const int2 *>(R.vs)[below(w.w[1], nv)];
+        a = ea.x;
+        rowa = ea.y;
+        b = eb.x;
+        rowb = eb.y;
         if (lane == 0) {
             R.parents[2 * p] = a;
             R.parents[2 * p + 1] = b;
@@ -459,9 +464,8 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             nocross = ((double)w.w[0] * 0x1p-32) > R.p_c;
         }
 
-        const int32_t *slot_row = slot_row_of(R, pop);
-        const float *x1row = R.X + (int64_t)slot_row[a] * R.ld;
-        const float *x2row = R.X + (int64_t)slot_row[b] * R.ld;
+        const float *x1row = R.X + (int64_t)rowa * R.ld;
+        const float *x2row = R.X + (int64_t)rowb * R.ld;
         float *c1row = R.X + (int64_t)R.off_row[o1] * R.ld;
         float *c2row = has2 ? R.X + (int64_t)R.off_row[o2] * R.ld : nullptr;
         const int Q = (R.d + 3) / 4;

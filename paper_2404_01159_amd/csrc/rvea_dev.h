@@ -46,7 +46,7 @@ struct RunView {
     float *Fms;         // 2 x M x m merged objectives (slots, then offspring)
     uint8_t *mvalid;    // M: row takes part in the selection
     int32_t *parents;   // ceil(N/2) x 2 slot indices
-    int32_t *vs;        // K valid slots, ascending
+    int32_t *vs;        // K x 2: valid slots, ascending, each with its physical row
     int32_t *nvalid;    // 1
     int32_t *stamp;     // K+N: the generation that will read the row (rows of
                         // the current population carry t_done + 1)

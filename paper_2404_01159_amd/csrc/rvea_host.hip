@@ -93,7 +93,7 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
     const size_t sz[B_COUNT] = {
         (size_t)(K + N) * L.ld * 4, (size_t)2 * K * 4, (size_t)N * 4, (size_t)2 * K,
         (size_t)2 * M * m * 4, (size_t)M,
-        (size_t)P * 2 * 4, (size_t)K * 4, 4, (size_t)(K + N) * 4, (size_t)K * m * 8,
+        (size_t)P * 2 * 4, (size_t)K * 8, 4, (size_t)(K + N) * 4, (size_t)K * m * 8,
         (size_t)K * m * 8, (size_t)K * L.stride * 4, (size_t)K * 8, (size_t)K * 8,
         (size_t)2 * m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
         (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4,
