@@ -112,14 +112,16 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
     for (int r = 0; r < RR; ++r) {
         const int64_t i = bx * (256 * RR) + r * 256 + threadIdx.x;
         rows[r] = i;
+        // the row's values load beside its take-part flag, not after it
+        float fr[MD];
+#pragma unroll
+        for (int k = 0; k < MD; ++k)
+            fr[k] = i < nrows ? (GAMMA ? R.V32[i * (NV4 * 4) + k] : Fm[i * MD + k]) : 0.f;
         const bool ok = i < nrows && (GAMMA || R.mvalid[i]);
         float n2 = 0.f;
 #pragma unroll
         for (int k = 0; k < MD; ++k) {
-            if (GAMMA)
-                f[r][k] = ok ? R.V32[i * (NV4 * 4) + k] : 0.f;
-            else
-                f[r][k] = ok ? Fm[i * MD + k] - z[k] : 0.f;
+            f[r][k] = ok ? (GAMMA ? fr[k] : fr[k] - z[k]) : 0.f;
             n2 = fmaf(f[r][k], f[r][k], n2);
         }
         e2[r] = two_eps(sqrtf(n2));
@@ -241,9 +243,25 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         const int c = sub + u * kLanes;
         cmax[u] = -INFINITY;
         cmask[u] = 0u;
-        if (act && c < R.KC) {
+        if (i < nrows && c < R.KC) {  // not waiting for the take-part flag
             cmax[u] = R.pmax[(int64_t)c * R.M + i];
             cmask[u] = R.pmask[(int64_t)c * R.M + i];
+        }
+    }
+    // the row's objectives (vector), also loaded beside the flag
+    double rv[MD];
+    float rf[MD];
+#pragma unroll
+    for (int k = 0; k < MD; ++k) {
+        rv[k] = 0.0;
+        rf[k] = 0.f;
+        if (i < nrows) {
+            if (GAMMA) {
+                rv[k] = R.V[i * MD + k];
+                rf[k] = R.V32[i * (MD <= 4 ? 4 : 8) + k];
+            } else {
+                rf[k] = fm_of(R, *R.t_done)[i * MD + k];
+            }
         }
     }
     if (act) {
@@ -253,11 +271,11 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         for (int k = 0; k < MD; ++k) {
             float fk;
             if (GAMMA) {
-                f[k] = R.V[i * MD + k];
-                fk = R.V32[i * (MD <= 4 ? 4 : 8) + k];
+                f[k] = rv[k];
+                fk = rf[k];
             } else {
                 const float zk = ord_dec(zbuf(R, *R.t_done + 1)[k]);
-                const float Fk = fm_of(R, *R.t_done)[i * MD + k];
+                const float Fk = rf[k];
                 f[k] = (double)Fk - (double)zk;
                 fk = Fk - zk;
             }
