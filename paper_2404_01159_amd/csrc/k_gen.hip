@@ -27,28 +27,6 @@ namespace rvea {
 // and writes its valid slots to their ascending positions, and reserves room
 // for its unstamped (free) rows with one atomic add.  The order of the free
 // rows does not matter: it only decides where each child's genes are stored.
-__device__ __forceinline__ int block_scan_256(int v, int *total)
-{
-    __shared__ int wsum[4];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    int before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        before += w < wid ? wsum[w] : 0;
-        tot += wsum[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return before + x - v;
-}
 
 // Prepare generation gen = t_done + 1 from population p = t_done (one
 // kernel): reset the selection's per-vector minima and the survivors'
@@ -61,10 +39,27 @@ __device__ __forceinline__ int block_scan_256(int v, int *total)
 __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
 {
     const int64_t j = bx * 256 + threadIdx.x;
+    // every load first: the row stamp and the earlier blocks' counts do not
+    // depend on the generation counter; the slot's flag, objectives and row do
+    const int32_t stampj = j < R.K + R.N ? R.stamp[j] : 0;
+    int pre = 0;  // valid slots of the earlier blocks (partial sum)
+    for (int b = threadIdx.x; b < (int)bx && b < (int)((R.K + 255) / 256); b += 256)
+        pre += R.bcount[b];
     const int64_t p = *R.t_done;
     const int32_t gen = (int32_t)(p + 1);
-    const uint8_t *valid = valid_of(R, p);
     const float *Fm = fm_of(R, p);
+    int v = 0;
+    int32_t rowj = 0;
+    float fj[kMaxM];
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k) fj[k] = 0.f;
+    if (j < R.K) {
+        v = valid_of(R, p)[j] ? 1 : 0;
+        rowj = slot_row_of(R, p)[j];
+#pragma unroll
+        for (int k = 0; k < kMaxM; ++k)
+            if (k < R.m) fj[k] = Fm[j * R.m + k];
+    }
     if (j < R.K) R.key[j] = ~0ull;
     if (j < R.m) {
         R.rbits[j] = 0xffffffffu;  // survivors' minimum
@@ -75,37 +70,61 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
     }
     __shared__ uint32_t zmin[kMaxM];
     if (threadIdx.x < kMaxM) zmin[threadIdx.x] = 0xffffffffu;
-    const int v = (j < R.K && valid[j]) ? 1 : 0;
     bool take = false;
     if (j < R.K) {
         bool fin = true;
-        for (int k = 0; k < R.m; ++k) fin = fin && isfinite(Fm[j * R.m + k]);
+#pragma unroll
+        for (int k = 0; k < kMaxM; ++k)
+            if (k < R.m) fin = fin && isfinite(fj[k]);
         if (v && !fin) atomicAdd(&R.counters[0], 1ull);
         take = v && fin;
         R.mvalid[j] = take ? 1 : 0;
     }
-    // offset of this block's valid slots
-    int pre = 0;
-    for (int b = threadIdx.x; b < (int)bx && b < (int)((R.K + 255) / 256); b += 256)
-        pre += R.bcount[b];
-    int offset;
-    (void)block_scan_256(pre, &offset);  // block total of the partial sums
-    for (int k = 0; k < R.m; ++k) {
-        const uint32_t e = wave_min(take ? ord_enc(Fm[j * R.m + k]) : 0xffffffffu);
-        if ((threadIdx.x & 63) == 0 && e != 0xffffffffu) atomicMin(&zmin[k], e);
+    const int fr = (j < R.K + R.N && stampj != gen) ? 1 : 0;
+    // the block's three sums in one scan: earlier blocks' valid slots, this
+    // block's valid slots (positions), its free rows (positions)
+    __shared__ int wsum[3][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x0 = pre, x1 = v, x2 = fr;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y0 = __shfl_up(x0, o, 64), y1 = __shfl_up(x1, o, 64), y2 = __shfl_up(x2, o, 64);
+        if (lane >= o) {
+            x0 += y0;
+            x1 += y1;
+            x2 += y2;
+        }
     }
-    int tot;
-    const int pos = block_scan_256(v, &tot);
+    if (lane == 63) {
+        wsum[0][wid] = x0;
+        wsum[1][wid] = x1;
+        wsum[2][wid] = x2;
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k) {
+        if (k < R.m) {
+            const uint32_t e = wave_min(take ? ord_enc(fj[k]) : 0xffffffffu);
+            if (lane == 0 && e != 0xffffffffu) atomicMin(&zmin[k], e);
+        }
+    }
+    __syncthreads();
+    int offset = 0, tot = 0, ftot = 0, before1 = 0, before2 = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        offset += wsum[0][w];
+        tot += wsum[1][w];
+        ftot += wsum[2][w];
+        before1 += w < wid ? wsum[1][w] : 0;
+        before2 += w < wid ? wsum[2][w] : 0;
+    }
+    const int pos = before1 + x1 - v, fpos = before2 + x2 - fr;
     if (v)  // the slot and its row: a parent's genes are one lookup away
-        reinterpret_cast<int2 *>(R.vs)[offset + pos] = make_int2((int32_t)j, slot_row_of(R, p)[j]);
+        reinterpret_cast<int2 *>(R.vs)[offset + pos] = make_int2((int32_t)j, rowj);
     const int64_t nblk = (R.K + 255) / 256;
     if (bx == nblk - 1 && threadIdx.x == 0) *R.nvalid = offset + tot;
     if (threadIdx.x < R.m && zmin[threadIdx.x] != 0xffffffffu)
         atomicMin(&zbuf(R, gen)[threadIdx.x], zmin[threadIdx.x]);
-    // free rows of this block
-    const int fr = (j < R.K + R.N && R.stamp[j] != gen) ? 1 : 0;
-    int ftot;
-    const int fpos = block_scan_256(fr, &ftot);
+    // free rows of this block: one atomic reserves their places
     __shared__ int fbase;
     if (threadIdx.x == 0) fbase = ftot ? atomicAdd(R.freecnt, ftot) : 0;
     __syncthreads();
