@@ -537,6 +537,10 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
 {
     __shared__ uint32_t smin[kMaxM], smax[kMaxM];
     __shared__ int wc[4];
+    const int64_t j = bx * 256 + threadIdx.x;
+    // the vector's key does not depend on the generation counter: both load
+    // together, then the survivor's row and objectives together
+    const unsigned long long kj = j < R.K ? R.key[j] : ~0ull;
     const int64_t g = *R.t_done + 1;
     if (threadIdx.x < kMaxM) {
         smin[threadIdx.x] = 0xffffffffu;
@@ -544,36 +548,41 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
     }
     if (bx == 0 && threadIdx.x < R.m) zbuf(R, g + 1)[threadIdx.x] = 0xffffffffu;
     if (bx == 0 && threadIdx.x == 0) *R.freecnt = 0;
-    __syncthreads();
-    const int64_t j = bx * 256 + threadIdx.x;
     const int32_t *row0 = slot_row_of(R, g - 1);
     const float *F0 = fm_of(R, g - 1);
     int32_t *row1 = slot_row_of(R, g);
     uint8_t *val1 = valid_of(R, g);
     float *F1 = fm_of(R, g);
-    int v = 0;
-    int32_t s = 0;
+    const int64_t si = (int64_t)(kj & ((1ull << R.kb) - 1));
+    const int v = (j < R.K && kj != ~0ull && si < R.M) ? 1 : 0;  // else no row for vector j
+    const int32_t s = v ? (int32_t)si : 0;
+    float fs[kMaxM];
+    int32_t row = 0;
+    if (v) {
+        row = s < R.K ? row0[s] : R.off_row[s - R.K];
+#pragma unroll
+        for (int k = 0; k < kMaxM; ++k)
+            if (k < R.m) fs[k] = F0[(int64_t)s * R.m + k];
+    }
+    __syncthreads();
     if (j < R.K) {
-        const unsigned long long kj = R.key[j];
-        const int64_t si = (int64_t)(kj & ((1ull << R.kb) - 1));
-        if (kj == ~0ull || si >= R.M) {  // no row associated with vector j
+        if (!v) {
             R.surv[j] = -1;
             val1[j] = 0;
             row1[j] = row0[j];
         } else {
-            s = (int32_t)si;
             R.surv[j] = s;
-            v = 1;
-            const int32_t row = s < R.K ? row0[s] : R.off_row[s - R.K];
             val1[j] = 1;
             row1[j] = row;
             R.stamp[row] = (int32_t)(g + 1);
         }
     }
-    for (int k = 0; k < R.m; ++k) {
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k) {
+        if (k >= R.m) break;
         uint32_t e = 0xffffffffu;
         if (j < R.K) {
-            const float x = v ? F0[(int64_t)s * R.m + k] : __int_as_float(0x7fc00000);
+            const float x = v ? fs[k] : __int_as_float(0x7fc00000);
             F1[j * R.m + k] = x;
             if (v) e = ord_enc(x);
         }
