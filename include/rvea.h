@@ -226,6 +226,16 @@ rvea_status rvea_get_counters(rvea_run run, rvea_counters *out);
 rvea_status rvea_set_timing(rvea_run run, int kernel_mask);
 rvea_status rvea_kernel_time(rvea_run run, int kernel, double *ms, int64_t *launches);
 
+/* Launch time of the three hot kernels without per-launch event overhead:
+ * between rvea_step and rvea_select, each of reproduce+evaluate (id 0; the
+ * policy rollouts excluded), association and re-rank is launched reps times
+ * back to back on the current state between two HIP events; ms[0..2]
+ * receives milliseconds per launch.  Every launch rewrites the same outputs
+ * from the same inputs, so the state and the counters are as before; the
+ * call waits for the stream.  RVEA_ESTATE outside that phase, in a batch or
+ * with kernel timing on. */
+rvea_status rvea_time_kernels(rvea_run run, int reps, double *ms);
+
 /* Association tile autotuner.  The association pass (Alg. 1's angle
  * computation, Eq. 2) can run with 1, 2 or 4 rows per lane and with vector
  * chunks of 32..1024 vectors (at least the default length; fewer chunks mean

@@ -841,6 +841,39 @@ rvea_status rvea_kernel_time(rvea_run r, int kernel, double *ms, int64_t *launch
     return RVEA_OK;
 }
 
+rvea_status rvea_time_kernels(rvea_run r, int reps, double *ms)
+{
+    if (!r || reps < 1 || !ms) return RVEA_EINVAL;
+    if (r->phase != 1 || r->batch || r->timing) return RVEA_ESTATE;
+    const RunView &R = r->R;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    unsigned long long saved[3];
+    HIPCHK(r, hipMemcpy(saved, R.counters, sizeof saved, hipMemcpyDeviceToHost));
+    hipEvent_t a = take_event(r), b = take_event(r);
+    if (!a || !b) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
+    // each pass rewrites the same outputs from the same inputs: the
+    // offspring from the parents, the partials from F and V, and the
+    // re-rank's minima (order-free) from the partials
+    for (int k = 0; k < 3; ++k) {
+        auto launch = [&]() {
+            return k == 0 ? launch_offspring(R, r->stream)
+                          : (k == 1 ? launch_assoc(R, r->stream) : launch_rerank(R, r->stream));
+        };
+        HIPCHK(r, launch());  // warm
+        HIPCHK(r, hipEventRecord(a, r->stream));
+        for (int i = 0; i < reps; ++i) HIPCHK(r, launch());
+        HIPCHK(r, hipEventRecord(b, r->stream));
+        HIPCHK(r, hipEventSynchronize(b));
+        float x = 0.f;
+        HIPCHK(r, hipEventElapsedTime(&x, a, b));
+        ms[k] = (double)x / reps;
+    }
+    r->pool.push_back(a);
+    r->pool.push_back(b);
+    HIPCHK(r, hipMemcpy(R.counters, saved, sizeof saved, hipMemcpyHostToDevice));
+    return RVEA_OK;
+}
+
 rvea_status rvea_batch_retire(rvea_batch b, rvea_run r);
 
 

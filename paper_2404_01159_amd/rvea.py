@@ -29,7 +29,8 @@ EXPORTS = [
     "rvea_get_state",
     "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
     "rvea_get_counters",
-    "rvea_set_timing", "rvea_kernel_time", "rvea_autotune", "rvea_synchronize", "rvea_destroy",
+    "rvea_set_timing", "rvea_kernel_time", "rvea_time_kernels", "rvea_autotune",
+    "rvea_synchronize", "rvea_destroy",
     "rvea_status_str", "rvea_last_error",
     "rvea_batch_footprint", "rvea_batch_create", "rvea_batch_admit", "rvea_batch_retire",
     "rvea_batch_step", "rvea_batch_set_graphs", "rvea_batch_size", "rvea_batch_synchronize",
@@ -93,6 +94,7 @@ def _load():
         "rvea_get_counters": [P, P],
         "rvea_set_timing": [P, i32],
         "rvea_kernel_time": [P, i32, P, P],
+        "rvea_time_kernels": [P, i32, P],
         "rvea_autotune": [P, P],
         "rvea_synchronize": [P], "rvea_destroy": [P],
     }
@@ -309,6 +311,14 @@ class Run:
         self._chk(lib.rvea_kernel_time(self._h, kernel, C.byref(ms), C.byref(n)),
                   "rvea_kernel_time")
         return ms.value, n.value
+
+    def time_kernels(self, reps=20):
+        """Per-launch ms of reproduce+evaluate, association and re-rank, each
+        launched reps times back to back on the current state (call between
+        step() and select(); state unchanged)."""
+        ms = (C.c_double * 3)()
+        self._chk(lib.rvea_time_kernels(self._h, reps, ms), "rvea_time_kernels")
+        return dict(offspring=ms[0], assoc=ms[1], rerank=ms[2])
 
     def close(self):
         if self._h:

@@ -91,6 +91,7 @@ def test_null_handles_and_status_strings(P):
         assert getattr(R.lib, fn)(None) == R.RVEA_EINVAL
     assert R.lib.rvea_run_generations(None, 1) == R.RVEA_EINVAL
     assert R.lib.rvea_prepare_generations(None, 1) == R.RVEA_EINVAL
+    assert R.lib.rvea_time_kernels(None, 1, None) == R.RVEA_EINVAL
     assert R.lib.rvea_status_str(0) == b"ok"
     assert R.lib.rvea_status_str(-4) == b"call out of order"
     assert R.lib.rvea_last_error(None) == b"no run"

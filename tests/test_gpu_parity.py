@@ -350,6 +350,29 @@ def test_kernel_timing_records_launches(P):
     assert n == 1
 
 
+def test_kernel_relaunch_timing_leaves_state(P):
+    """rvea_time_kernels re-launches the hot kernels on the current state:
+    the generation continues exactly as without it."""
+    a = P.Run(1, 3, 60, 300, 300, seed=8, params=P.default_params(t_max=20))
+    b = P.Run(1, 3, 60, 300, 300, seed=8, params=P.default_params(t_max=20))
+    for r in (a, b):
+        r.run(3)
+        r.step()
+    t = b.time_kernels(5)
+    assert all(t[k] > 0 for k in ("offspring", "assoc", "rerank"))
+    for r in (a, b):
+        r.select()
+        r.adapt()
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("X", "F", "valid", "V", "gamma", "t"):
+        assert np.array_equal(sa[k], sb[k], equal_nan=True), k
+    assert a.counters() == b.counters()
+    with pytest.raises(P.RveaError):
+        b.time_kernels(5)  # only between step and select
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("shape", [(1, 3, 40, 1200, 1225), (2, 2, 30, 4000, 4096),
                                    (3, 5, 25, 1001, 1001)])
 def test_autotuned_tiles_give_identical_runs(P, O, shape):
