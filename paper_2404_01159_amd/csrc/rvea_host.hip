@@ -192,22 +192,39 @@ hipEvent_t take_event(rvea_run r)
     return e;
 }
 
+// two events from the run's pool, handed back when the holder goes out of
+// scope unless keep() passed them on
+struct EventPair {
+    rvea_run r;
+    hipEvent_t a, b;
+    explicit EventPair(rvea_run r_) : r(r_), a(take_event(r_)), b(take_event(r_)) {}
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    ~EventPair()
+    {
+        if (a) r->pool.push_back(a);
+        if (b) r->pool.push_back(b);
+    }
+    bool ok() const { return a && b; }
+    void keep() { a = b = nullptr; }
+};
+
 // launches fn; when timing is on, brackets it with events on the run's stream
 template <class Fn>
 rvea_status timed(rvea_run r, int id, Fn fn, const char *what)
 {
-    hipEvent_t a = nullptr, b = nullptr;
-    const bool on = (r->timing >> id) & 1;
-    if (on) {
-        a = take_event(r);
-        b = take_event(r);
-        if (a && b) HIPCHK(r, hipEventRecord(a, r->stream));
+    if (!((r->timing >> id) & 1)) {
+        hipError_t e = fn();
+        return e == hipSuccess ? RVEA_OK : fail(r, e, what);
     }
+    EventPair ev(r);
+    if (ev.ok()) HIPCHK(r, hipEventRecord(ev.a, r->stream));
     hipError_t e = fn();
     if (e != hipSuccess) return fail(r, e, what);
-    if (on && a && b) {
-        HIPCHK(r, hipEventRecord(b, r->stream));
-        r->events.push_back({id, a, b});
+    if (ev.ok()) {
+        HIPCHK(r, hipEventRecord(ev.b, r->stream));
+        r->events.push_back({id, ev.a, ev.b});
+        ev.keep();
     }
     return RVEA_OK;
 }
@@ -849,8 +866,9 @@ rvea_status rvea_time_kernels(rvea_run r, int reps, double *ms)
     HIPCHK(r, hipStreamSynchronize(r->stream));
     unsigned long long saved[3];
     HIPCHK(r, hipMemcpy(saved, R.counters, sizeof saved, hipMemcpyDeviceToHost));
-    hipEvent_t a = take_event(r), b = take_event(r);
-    if (!a || !b) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
+    EventPair ev(r);
+    if (!ev.ok()) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
+    const hipEvent_t a = ev.a, b = ev.b;
     // each pass rewrites the same outputs from the same inputs: the
     // offspring from the parents, the partials from F and V, and the
     // re-rank's minima (order-free) from the partials
@@ -868,8 +886,6 @@ rvea_status rvea_time_kernels(rvea_run r, int reps, double *ms)
         HIPCHK(r, hipEventElapsedTime(&x, a, b));
         ms[k] = (double)x / reps;
     }
-    r->pool.push_back(a);
-    r->pool.push_back(b);
     HIPCHK(r, hipMemcpy(R.counters, saved, sizeof saved, hipMemcpyHostToDevice));
     return RVEA_OK;
 }
@@ -926,8 +942,9 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     HIPCHK(r, launch_prepare(R, r->stream));
     HIPCHK(r, launch_offspring(R, r->stream));
     if (R.problem == kPolicy) HIPCHK(r, launch_rollout(R, r->stream, true));
-    hipEvent_t a = take_event(r), b = take_event(r);
-    if (!a || !b) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
+    EventPair ev(r);
+    if (!ev.ok()) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
+    const hipEvent_t a = ev.a, b = ev.b;
     struct Cand {
         int rr, cs;
         float ms;  // association + re-rank
@@ -1003,7 +1020,7 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     // the gamma pass (rows = vectors, at adaptations): its own chunking and
     // rows per lane, timed on the current vectors (it rewrites the same
     // gamma every time)
-    const int grr0 = R.grr, gcs0 = R.gCS, gkc0 = R.gKC;
+    const int grr0 = R.grr, gcs0 = R.gCS;
     double g_def = -1.0, g_best = 1e30;
     int g_rr = grr0, g_cs = gcs0;
     int ncand = (int)cands.size() + 3;
@@ -1038,9 +1055,6 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     R.grr = g_rr;
     R.gCS = g_cs;
     R.gKC = (int)((R.K + g_cs - 1) / g_cs);
-    (void)gkc0;
-    r->pool.push_back(a);
-    r->pool.push_back(b);
     HIPCHK(r, hipMemcpy(R.counters, saved, sizeof saved, hipMemcpyHostToDevice));
     // the trial's preparation handed out free rows: the real one starts over
     HIPCHK(r, hipMemsetAsync(R.freecnt, 0, 4, r->stream));
