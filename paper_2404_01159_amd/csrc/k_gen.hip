@@ -597,8 +597,10 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             pos1[k] = __shfl(pv1[k & 3], k >> 2, S);
             pos2[k] = __shfl(pv2[k & 3], k >> 2, S);
         }
-        if (lane == 0 && evaluate) {
-            // objectives; rows that take part (finite F) and their LDS minima
+        if (evaluate && (lane == 0 || (lane == 1 && has2))) {
+            // objectives, child 1 on lane 0 and child 2 on lane 1 (two lanes
+            // finish them side by side); rows that take part (finite F) and
+            // their LDS minima
             auto emit = [&](const float(&pos)[kMaxM], double gs, int64_t row) {
                 float f[kMaxM];
                 finish_objectives(R.problem, R.m, R.d, pos, gs, f);
@@ -620,8 +622,11 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                 for (int k = 0; k < kMaxM; ++k)
                     if (k < R.m) atomicMin(&szmin[k], ord_enc(f[k]));
             };
-            emit(pos1, g1, R.K + o1);
-            if (has2) emit(pos2, g2, R.K + o2);
+            float pos[kMaxM];
+#pragma unroll
+            for (int k = 0; k < kMaxM - 1; ++k) pos[k] = lane == 0 ? pos1[k] : pos2[k];
+            pos[kMaxM - 1] = 0.f;
+            emit(pos, lane == 0 ? g1 : g2, R.K + (lane == 0 ? o1 : o2));
         }
     }
     // the workgroup's share of the ideal point: one guarded atomic per
@@ -630,7 +635,10 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     if (evaluate && threadIdx.x < R.m) {
         const uint32_t e = szmin[threadIdx.x];
         uint32_t *zb = zbuf(R, t);
-        if (e < *(volatile uint32_t *)&zb[threadIdx.x]) atomicMin(&zb[threadIdx.x], e);
+        // a relaxed atomic read: unlike a volatile one it does not wait for
+        // the wavefront's outstanding stores
+        if (e < __hip_atomic_load(&zb[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMin(&zb[threadIdx.x], e);
     }
 }
 

@@ -219,7 +219,9 @@ __device__ __forceinline__ void child_ideal(const RunView &R, int64_t gen, bool 
     uint32_t *zb = zbuf(R, gen);
     for (int k = 0; k < R.m; ++k) {
         const uint32_t e = wave_min(ok ? ord_enc(f[k]) : 0xffffffffu);
-        if ((threadIdx.x & 63) == 0 && e < *(volatile uint32_t *)&zb[k]) atomicMin(&zb[k], e);
+        if ((threadIdx.x & 63) == 0 &&
+            e < __hip_atomic_load(&zb[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMin(&zb[k], e);
     }
 }
 
