@@ -360,6 +360,8 @@ def test_kernel_relaunch_timing_leaves_state(P):
         r.step()
     t = b.time_kernels(5)
     assert all(t[k] > 0 for k in ("offspring", "assoc", "rerank"))
+    t = b.time_kernels(3)  # again in the same phase: its events come back to the pool
+    assert all(t[k] > 0 for k in ("offspring", "assoc", "rerank"))
     for r in (a, b):
         r.select()
         r.adapt()
