@@ -243,8 +243,9 @@ rvea_status rvea_time_kernels(rvea_run run, int reps, double *ms);
  * with 4, 8 or 16 rows per wavefront.  Association shapes are timed together
  * with the re-rank that reads their partials.  rvea_autotune draws the
  * next generation's offspring and ideal point without committing anything,
- * times every candidate on them with HIP events (best of three launches) and
- * keeps the fastest for the rest of the run.  The adaptation's gamma pass
+ * times every candidate on them (five launches back to back between two HIP
+ * events, per-launch time, best of two such rounds) and keeps the fastest
+ * for the rest of the run.  The adaptation's gamma pass
  * (its rows are the K vectors) gets its own rows per lane and chunk length,
  * timed the same way on the current vectors.  Results do not depend on the choice: the association is
  * finished in binary64 over candidate tiles.  Needs the run between
@@ -256,7 +257,7 @@ typedef struct rvea_tuning {
     int32_t chunk_vectors;      /* association: chosen chunk length */
     int32_t rerank_rows;        /* binary64 re-rank: chosen rows per wavefront (4, 8, 16) */
     int32_t candidates;         /* configurations timed */
-    double assoc_us;            /* association + re-rank, chosen shape (best of three) */
+    double assoc_us;            /* association + re-rank per launch, chosen shape */
     double default_us;          /* association + re-rank, default shape */
     double rerank_us;           /* best time of the chosen re-rank configuration */
     double rerank_default_us;   /* best time of the default one */

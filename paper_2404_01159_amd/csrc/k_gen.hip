@@ -450,20 +450,18 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     }
 
     // random mating: two uniform draws over the valid slots
-    int32_t a = 0, b = 0, rowa = 0, rowb = 0;
-    if (active) {
-        const W4 w = draw(R, 0u, (uint32_t)p, t, TAG_MATE);
-        const int2 ea = reinterpret_cast<const int2 *>(R.vs)[below(w.w[0], nv)];
-        const int2 eb = reinterpret_cast<const int2 *>(R.vs)[below(w.w[1], nv)];
-        a = ea.x;
-        rowa = ea.y;
-        b = eb.x;
-        rowb = eb.y;
-        if (lane == 0) {
-            R.parents[2 * p] = a;
-            R.parents[2 * p + 1] = b;
-        }
-    }
+    // (inactive segments draw too and leave the values unused: without a
+    // conditional join the loads are waited for only where they are used)
+    const W4 wm = draw(R, 0u, (uint32_t)p, t, TAG_MATE);
+    const int2 ea = reinterpret_cast<const int2 *>(R.vs)[below(wm.w[0], nv)];
+    const int2 eb = reinterpret_cast<const int2 *>(R.vs)[below(wm.w[1], nv)];
+    const int32_t a = ea.x, rowa = ea.y, b = eb.x, rowb = eb.y;
+
+    // the children's rows: they do not depend on the mating, so their loads
+    // are issued before the sites are drawn (clamped indices for inactive
+    // segments and a missing second child, values unused)
+    const int32_t orow1 = R.off_row[active ? o1 : 0];
+    const int32_t orow2 = R.off_row[active && has2 ? o2 : 0];
 
     // mutation sites of both children
     int n1 = 0, n2 = 0;
@@ -485,8 +483,8 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
 
         const float *x1row = R.X + (int64_t)rowa * R.ld;
         const float *x2row = R.X + (int64_t)rowb * R.ld;
-        float *c1row = R.X + (int64_t)R.off_row[o1] * R.ld;
-        float *c2row = has2 ? R.X + (int64_t)R.off_row[o2] * R.ld : nullptr;
+        float *c1row = R.X + (int64_t)orow1 * R.ld;
+        float *c2row = has2 ? R.X + (int64_t)orow2 * R.ld : nullptr;
         const int Q = (R.d + 3) / 4;
         const double lb = R.lb, ub = R.ub;
         const double np1 = R.eta_c + 1.0;
@@ -639,6 +637,12 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         // the wavefront's outstanding stores
         if (e < __hip_atomic_load(&zb[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMin(&zb[threadIdx.x], e);
+    }
+    // the parents' slots (kept for the host): stored last, so that no wait
+    // for an earlier load also waits for this store
+    if (active && lane == 0) {
+        R.parents[2 * p] = a;
+        R.parents[2 * p + 1] = b;
     }
 }
 

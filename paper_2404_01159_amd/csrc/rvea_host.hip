@@ -945,6 +945,27 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     EventPair ev(r);
     if (!ev.ok()) return fail(r, hipErrorOutOfMemory, "hipEventCreate");
     const hipEvent_t a = ev.a, b = ev.b;
+    // a candidate's time per launch: kTuneReps launches back to back between
+    // two events (no per-launch event overhead), best of two rounds, after a
+    // warm launch; every timed pass rewrites the same outputs
+    constexpr int kTuneReps = 5;
+    auto time_launches = [&](auto &&launch, float *out) -> hipError_t {
+        hipError_t e = launch();
+        if (e != hipSuccess) return e;
+        float best = 1e30f;
+        for (int round = 0; round < 2; ++round) {
+            if ((e = hipEventRecord(a, r->stream)) != hipSuccess) return e;
+            for (int i = 0; i < kTuneReps; ++i)
+                if ((e = launch()) != hipSuccess) return e;
+            if ((e = hipEventRecord(b, r->stream)) != hipSuccess) return e;
+            if ((e = hipEventSynchronize(b)) != hipSuccess) return e;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) return e;
+            best = std::min(best, ms / kTuneReps);
+        }
+        *out = best;
+        return hipSuccess;
+    };
     struct Cand {
         int rr, cs;
         float ms;  // association + re-rank
@@ -963,19 +984,13 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
         if (R.KC > KC0) continue;  // the workspace holds KC0 chunk partials
         // the chunk count also sets the re-rank's work (partials per row),
         // so each candidate is timed with the re-rank that follows it
-        HIPCHK(r, launch_assoc(R, r->stream));  // warm
-        HIPCHK(r, launch_rerank(R, r->stream));
-        float best = 1e30f;
-        for (int rep_ = 0; rep_ < 3; ++rep_) {
-            HIPCHK(r, hipEventRecord(a, r->stream));
-            HIPCHK(r, launch_assoc(R, r->stream));
-            HIPCHK(r, launch_rerank(R, r->stream));
-            HIPCHK(r, hipEventRecord(b, r->stream));
-            HIPCHK(r, hipEventSynchronize(b));
-            float ms = 0.f;
-            HIPCHK(r, hipEventElapsedTime(&ms, a, b));
-            best = std::min(best, ms);
-        }
+        float best = 0.f;
+        HIPCHK(r, time_launches(
+                      [&]() {
+                          const hipError_t e = launch_assoc(R, r->stream);
+                          return e != hipSuccess ? e : launch_rerank(R, r->stream);
+                      },
+                      &best));
         c.ms = best;
         if (c.rr == saved_rr && c.cs == saved_cs) def_ms = best;
     }
@@ -999,17 +1014,8 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     int rk_win = rk0;
     for (int rk : {4, 8, 16}) {
         R.rk = rk;
-        HIPCHK(r, launch_rerank(R, r->stream));  // warm
-        float best = 1e30f;
-        for (int rep_ = 0; rep_ < 3; ++rep_) {
-            HIPCHK(r, hipEventRecord(a, r->stream));
-            HIPCHK(r, launch_rerank(R, r->stream));
-            HIPCHK(r, hipEventRecord(b, r->stream));
-            HIPCHK(r, hipEventSynchronize(b));
-            float ms = 0.f;
-            HIPCHK(r, hipEventElapsedTime(&ms, a, b));
-            best = std::min(best, ms);
-        }
+        float best = 0.f;
+        HIPCHK(r, time_launches([&]() { return launch_rerank(R, r->stream); }, &best));
         if (rk == rk0) rk_def = best;
         if (best < rk_best) {
             rk_best = best;
@@ -1031,17 +1037,8 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
                 R.grr = rr;
                 R.gCS = cs;
                 R.gKC = kc;
-                HIPCHK(r, launch_gamma(R, r->stream, 1));  // warm
-                float best = 1e30f;
-                for (int rep_ = 0; rep_ < 3; ++rep_) {
-                    HIPCHK(r, hipEventRecord(a, r->stream));
-                    HIPCHK(r, launch_gamma(R, r->stream, 1));
-                    HIPCHK(r, hipEventRecord(b, r->stream));
-                    HIPCHK(r, hipEventSynchronize(b));
-                    float ms = 0.f;
-                    HIPCHK(r, hipEventElapsedTime(&ms, a, b));
-                    best = std::min(best, ms);
-                }
+                float best = 0.f;
+                HIPCHK(r, time_launches([&]() { return launch_gamma(R, r->stream, 1); }, &best));
                 ++ncand;
                 if (rr == grr0 && cs == gcs0) g_def = best;
                 if (best < g_best) {
