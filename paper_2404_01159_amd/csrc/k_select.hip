@@ -529,8 +529,9 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
 // each pair: slot j <- its survivor's gene row and objectives, or empty; the
 // survivor is the row index held in the vector's key.  The same pass stamps
 // the rows generation g+1 will read, counts valid slots per block (the next
-// preparation's offsets), reduces the survivors' extremes for a possible
-// adaptation, and clears generation g+1's ideal point and free-row counter.
+// preparation's offsets), reduces the survivors' extremes when an
+// adaptation follows, and clears generation g+1's ideal point and free-row
+// counter.
 // The last workgroup to finish counts the generation (t_done = g): every
 // workgroup has read t_done before it reports.
 __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
@@ -577,6 +578,10 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
             R.stamp[row] = (int32_t)(g + 1);
         }
     }
+    // the survivors' extremes feed only an adaptation right after this
+    // generation (g a multiple of the period): other generations skip the
+    // reductions (uniform branch)
+    const bool ext = g % R.period == 0;
 #pragma unroll
     for (int k = 0; k < kMaxM; ++k) {
         if (k >= R.m) break;
@@ -586,17 +591,19 @@ __device__ __forceinline__ void newpop_body(const RunView &R, int64_t bx)
             F1[j * R.m + k] = x;
             if (v) e = ord_enc(x);
         }
-        const uint32_t lo = wave_min(e);
-        const uint32_t hi = wave_max(e == 0xffffffffu ? 0u : e);
-        if ((threadIdx.x & 63) == 0) {
-            if (lo != 0xffffffffu) atomicMin(&smin[k], lo);
-            atomicMax(&smax[k], hi);
+        if (ext) {
+            const uint32_t lo = wave_min(e);
+            const uint32_t hi = wave_max(e == 0xffffffffu ? 0u : e);
+            if ((threadIdx.x & 63) == 0) {
+                if (lo != 0xffffffffu) atomicMin(&smin[k], lo);
+                atomicMax(&smax[k], hi);
+            }
         }
     }
     const unsigned long long b = __ballot(v);
     if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(b);
     __syncthreads();
-    if (threadIdx.x < R.m) {
+    if (ext && threadIdx.x < R.m) {
         if (smin[threadIdx.x] != 0xffffffffu) atomicMin(&R.rbits[threadIdx.x], smin[threadIdx.x]);
         atomicMax(&R.rbits[R.m + threadIdx.x], smax[threadIdx.x]);
     }
