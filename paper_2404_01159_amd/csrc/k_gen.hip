@@ -68,8 +68,6 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
     if (j == 0) {  // Eq. 4 penalty factor m (t/t_max)^alpha of this generation
         *R.pen = (double)R.m * pow((double)gen / (double)R.t_max, R.alpha);
     }
-    __shared__ uint32_t zmin[kMaxM];
-    if (threadIdx.x < kMaxM) zmin[threadIdx.x] = 0xffffffffu;
     bool take = false;
     if (j < R.K) {
         bool fin = true;
@@ -100,11 +98,14 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
         wsum[1][wid] = x1;
         wsum[2][wid] = x2;
     }
+    // each wavefront's minima in a slot of its own (no shared initial value
+    // that another wavefront could reach first), merged after the barrier
+    __shared__ uint32_t zw[4][kMaxM];
 #pragma unroll
     for (int k = 0; k < kMaxM; ++k) {
         if (k < R.m) {
             const uint32_t e = wave_min(take ? ord_enc(fj[k]) : 0xffffffffu);
-            if (lane == 0 && e != 0xffffffffu) atomicMin(&zmin[k], e);
+            if (lane == 0) zw[wid][k] = e;
         }
     }
     __syncthreads();
@@ -122,8 +123,11 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
         reinterpret_cast<int2 *>(R.vs)[offset + pos] = make_int2((int32_t)j, rowj);
     const int64_t nblk = (R.K + 255) / 256;
     if (bx == nblk - 1 && threadIdx.x == 0) *R.nvalid = offset + tot;
-    if (threadIdx.x < R.m && zmin[threadIdx.x] != 0xffffffffu)
-        atomicMin(&zbuf(R, gen)[threadIdx.x], zmin[threadIdx.x]);
+    if (threadIdx.x < R.m) {
+        const int k = threadIdx.x;
+        const uint32_t e = min(min(zw[0][k], zw[1][k]), min(zw[2][k], zw[3][k]));
+        if (e != 0xffffffffu) atomicMin(&zbuf(R, gen)[k], e);
+    }
     // free rows of this block: one atomic reserves their places
     __shared__ int fbase;
     if (threadIdx.x == 0) fbase = ftot ? atomicAdd(R.freecnt, ftot) : 0;
