@@ -180,18 +180,38 @@ __device__ __forceinline__ float ord_dec(uint32_t e)
     return __uint_as_float(u);
 }
 
-// wave-wide minimum / maximum of an ordered encoding
+// Wave-wide minimum / maximum of an ordered encoding, for a converged
+// wavefront: four DPP steps give every row of 16 lanes its extreme (swaps
+// within quads, then the half-row and row mirrors), and the four rows'
+// values are read out and combined as scalars (the result is uniform).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
+    v = min(v, dpp_u32<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = min(v, dpp_u32<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = min(v, dpp_u32<0x141>(v));  // row_half_mirror
+    v = min(v, dpp_u32<0x140>(v));  // row_mirror
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, d));
 }
 __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
+    v = max(v, dpp_u32<0xB1>(v));
+    v = max(v, dpp_u32<0x4E>(v));
+    v = max(v, dpp_u32<0x141>(v));
+    v = max(v, dpp_u32<0x140>(v));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, d));
 }
 
 // Ideal point z* of generation gen (Alg. 1): two buffers alternate by
