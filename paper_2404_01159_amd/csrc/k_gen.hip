@@ -65,9 +65,10 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
         R.rbits[j] = 0xffffffffu;  // survivors' minimum
         R.rbits[R.m + j] = 0u;     // survivors' maximum
     }
-    if (j == 0) {  // Eq. 4 penalty factor m (t/t_max)^alpha of this generation
+    // Eq. 4 penalty factor m (t/t_max)^alpha of this generation, computed by
+    // the last block (free rows only, the least work), off the others' path
+    if (bx == (R.K + R.N + 255) / 256 - 1 && threadIdx.x == 0)
         *R.pen = (double)R.m * pow((double)gen / (double)R.t_max, R.alpha);
-    }
     bool take = false;
     if (j < R.K) {
         bool fin = true;
