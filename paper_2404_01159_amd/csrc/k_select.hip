@@ -177,6 +177,51 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
     }
 }
 
+// Partner of each lane at level L of a reduction over groups of 32 lanes,
+// every lane active: swaps within quads, the half-row and row mirrors (DPP),
+// then the other half of the 32 (a swizzle, xor 16).  Each level pairs two
+// sub-groups whose lanes already agree, so after the five levels every lane
+// holds its group's result.
+template <int L>
+__device__ __forceinline__ int partner32(int v)
+{
+    if constexpr (L == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
+    else if constexpr (L == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
+    else if constexpr (L == 2) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+    else if constexpr (L == 3) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+    else return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // and 0x1f, xor 0x10
+}
+template <int L>
+__device__ __forceinline__ double partner32(double x)
+{
+    const int lo = partner32<L>(__double2loint(x)), hi = partner32<L>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+template <int L>
+__device__ __forceinline__ int64_t partner32(int64_t x)
+{
+    const uint32_t lo = (uint32_t)partner32<L>((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)partner32<L>((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// one level of the best-cosine reduction (largest value, lowest index on
+// ties; the item's gamma travels with it; duplicates are or-ed)
+template <int L, bool GAMMA>
+__device__ __forceinline__ void best_level(double &best, int64_t &bj, double &gam, int &dup)
+{
+    const double ob = partner32<L>(best);
+    const int64_t oj = partner32<L>(bj);
+    double og = 0.0;
+    if (!GAMMA) og = partner32<L>(gam);
+    dup |= partner32<L>(dup);
+    if (ob > best || (ob == best && oj < bj)) {
+        best = ob;
+        bj = oj;
+        gam = og;
+    }
+}
+
 template <int MD>
 __device__ __forceinline__ double dotd(const double *a, const double *b)
 {
@@ -395,19 +440,11 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
                 }
             }
         }
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o, 32);
-            const int64_t oj = __shfl_xor(bj, o, 32);
-            double og = 0.0;
-            if (!GAMMA) og = __shfl_xor(gam, o, 32);
-            dup |= __shfl_xor(dup, o, 32);
-            if (ob > best || (ob == best && oj < bj)) {
-                best = ob;
-                bj = oj;
-                gam = og;
-            }
-        }
+        best_level<0, GAMMA>(best, bj, gam, dup);
+        best_level<1, GAMMA>(best, bj, gam, dup);
+        best_level<2, GAMMA>(best, bj, gam, dup);
+        best_level<3, GAMMA>(best, bj, gam, dup);
+        best_level<4, GAMMA>(best, bj, gam, dup);
         if ((t & 31) == 0 && item < total) {
             s_best[item] = best;
             s_gam[item] = gam;
