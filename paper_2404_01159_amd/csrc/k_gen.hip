@@ -279,12 +279,27 @@ __device__ __forceinline__ double sbx_beta(double mc, double eta, int nrt)
     return sbx_beta_pow(mc, eta);
 }
 
-// Sum over the S lanes of a segment (S a power of two <= 64).
+// Sum over the S lanes of a segment (S a power of two, 4 <= S <= 64; a
+// segment's lanes are all active or all inactive): the pairings of
+// partner32, which stay within groups of S lanes, then for a whole
+// wavefront the two halves' sums read out and added.  Every lane of the
+// segment ends with the same value.
 template <int S>
 __device__ __forceinline__ double seg_sum(double v)
 {
-#pragma unroll
-    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, S);
+    static_assert(S >= 4 && S <= 64 && (S & (S - 1)) == 0, "segment width");
+    v += partner32<0>(v);
+    v += partner32<1>(v);
+    if constexpr (S >= 8) v += partner32<2>(v);
+    if constexpr (S >= 16) v += partner32<3>(v);
+    if constexpr (S >= 32) v += partner32<4>(v);
+    if constexpr (S == 64) {
+        const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                          __builtin_amdgcn_readlane(__double2loint(v), 0));
+        const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                          __builtin_amdgcn_readlane(__double2loint(v), 32));
+        v = a + b;
+    }
     return v;
 }
 

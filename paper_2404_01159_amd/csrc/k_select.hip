@@ -177,34 +177,6 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
     }
 }
 
-// Partner of each lane at level L of a reduction over groups of 32 lanes,
-// every lane active: swaps within quads, the half-row and row mirrors (DPP),
-// then the other half of the 32 (a swizzle, xor 16).  Each level pairs two
-// sub-groups whose lanes already agree, so after the five levels every lane
-// holds its group's result.
-template <int L>
-__device__ __forceinline__ int partner32(int v)
-{
-    if constexpr (L == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
-    else if constexpr (L == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
-    else if constexpr (L == 2) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
-    else if constexpr (L == 3) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
-    else return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // and 0x1f, xor 0x10
-}
-template <int L>
-__device__ __forceinline__ double partner32(double x)
-{
-    const int lo = partner32<L>(__double2loint(x)), hi = partner32<L>(__double2hiint(x));
-    return __hiloint2double(hi, lo);
-}
-template <int L>
-__device__ __forceinline__ int64_t partner32(int64_t x)
-{
-    const uint32_t lo = (uint32_t)partner32<L>((int)(uint32_t)x);
-    const uint32_t hi = (uint32_t)partner32<L>((int)(uint32_t)((uint64_t)x >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 // one level of the best-cosine reduction (largest value, lowest index on
 // ties; the item's gamma travels with it; duplicates are or-ed)
 template <int L, bool GAMMA>
