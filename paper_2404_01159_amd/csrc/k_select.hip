@@ -177,6 +177,27 @@ __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, 
     }
 }
 
+// maximum / sum over an aligned group of N adjacent lanes (N = 4, 8 or 16,
+// every lane active), by the pairings of partner32
+template <int N>
+__device__ __forceinline__ float group_max(float v)
+{
+    v = fmaxf(v, __int_as_float(partner32<0>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(partner32<1>(__float_as_int(v))));
+    if constexpr (N >= 8) v = fmaxf(v, __int_as_float(partner32<2>(__float_as_int(v))));
+    if constexpr (N >= 16) v = fmaxf(v, __int_as_float(partner32<3>(__float_as_int(v))));
+    return v;
+}
+template <int N>
+__device__ __forceinline__ int group_sum(int v)
+{
+    v += partner32<0>(v);
+    v += partner32<1>(v);
+    if constexpr (N >= 8) v += partner32<2>(v);
+    if constexpr (N >= 16) v += partner32<3>(v);
+    return v;
+}
+
 // one level of the best-cosine reduction (largest value, lowest index on
 // ties; the item's gamma travels with it; duplicates are or-ed)
 template <int L, bool GAMMA>
@@ -318,9 +339,8 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         thr = gm;
         if (!GAMMA) thr = gm - two_eps(sqrtf(n2f));
     }
-    // the four lanes of a row are adjacent: combine over xor 1, 2
-#pragma unroll
-    for (int o = 1; o < kLanes; o <<= 1) thr = fmaxf(thr, __shfl_xor(thr, o, 64));
+    // a row's lanes are adjacent and aligned: combine within the group
+    thr = group_max<kLanes>(thr);
     if (GAMMA && act && thr > -INFINITY) thr -= two_eps_dist(-thr);  // scores are -|v_i - v_j|^2
     // candidate tiles of this lane's chunks: those in registers, then any
     // further chunks (more than kCache per lane) read again
@@ -336,9 +356,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
             }
         }
     }
-    int tot = cnt;
-#pragma unroll
-    for (int o = 1; o < kLanes; o <<= 1) tot += __shfl_xor(tot, o, 64);
+    const int tot = group_sum<kLanes>(cnt);
     if (act && state == 1 && (tot < 1 || tot > kItems)) state = 3;
     // exclusive prefix of the tile counts over the row's four lanes
     int pre = cnt;  // inclusive scan over the row's lanes, then exclusive
