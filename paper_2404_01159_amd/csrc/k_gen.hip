@@ -84,16 +84,7 @@ __device__ __forceinline__ void prep_body(const RunView &R, int64_t bx)
     // block's valid slots (positions), its free rows (positions)
     __shared__ int wsum[3][4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x0 = pre, x1 = v, x2 = fr;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y0 = __shfl_up(x0, o, 64), y1 = __shfl_up(x1, o, 64), y2 = __shfl_up(x2, o, 64);
-        if (lane >= o) {
-            x0 += y0;
-            x1 += y1;
-            x2 += y2;
-        }
-    }
+    const int x0 = wave_incl_scan(pre), x1 = wave_incl_scan(v), x2 = wave_incl_scan(fr);
     if (lane == 63) {
         wsum[0][wid] = x0;
         wsum[1][wid] = x1;

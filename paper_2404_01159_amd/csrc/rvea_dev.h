@@ -208,6 +208,21 @@ __device__ __forceinline__ int64_t partner32(int64_t x)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Inclusive prefix sum over the 64 lanes of a converged wavefront (DPP):
+// shifts by 1, 2, 4 and 8 within each row of 16 lanes (lanes without a
+// source add 0), then each row adds the last lane of the rows before it
+// (row broadcasts of lanes 15 and 31).
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // Wave-wide minimum / maximum of an ordered encoding, for a converged
 // wavefront: four DPP steps give every row of 16 lanes its extreme (swaps
 // within quads, then the half-row and row mirrors), and the four rows'
