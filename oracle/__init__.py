@@ -106,6 +106,8 @@ def lib():
             "ora_generation": (i32, [P, i32, i32, i32, i64, i64, u64, i64, P, P, P, P, P, P,
                                      P, P, P, P, P]),
             "ora_run": (i32, [P, i32, i32, i32, i64, i64, u64, i32, P, P, P, P, P, P]),
+            "ora_hypervolume": (f64, [i32, i64, P, P, P, P]),
+            "ora_expected_utility": (f64, [i32, i64, P, P, P, P, i64, P]),
             "ora_num_threads": (i32, []),
             "ora_set_num_threads": (None, [i32]),
         }
@@ -427,6 +429,29 @@ def run(prm, problem, m, d, N, K, seed, gens):
     if rc != 0:
         raise RuntimeError(f"ora_run failed ({rc})")
     return State(X, F, valid, V, V0, g)
+
+
+def hypervolume(F, valid=None, lo=None, hi=None):
+    """App. C.2 hypervolume (m = 2, 3) with reference point ones on the
+    normalised objectives (F - lo) / (hi - lo); lo = 0, hi = 1 by default."""
+    F = _c(F, np.float64)
+    n, m = F.shape
+    lo = _c(np.zeros(m) if lo is None else lo, np.float64)
+    hi = _c(np.ones(m) if hi is None else hi, np.float64)
+    v = None if valid is None else _c(valid, np.uint8)
+    return float(lib().ora_hypervolume(m, n, _p(F), _p(v), _p(lo), _p(hi)))
+
+
+def expected_utility(F, W, valid=None, lo=None, hi=None):
+    """Mean over the weight rows W of the best utility -w . f' (f' as above)."""
+    F = _c(F, np.float64)
+    W = _c(W, np.float64)
+    n, m = F.shape
+    lo = _c(np.zeros(m) if lo is None else lo, np.float64)
+    hi = _c(np.ones(m) if hi is None else hi, np.float64)
+    v = None if valid is None else _c(valid, np.uint8)
+    return float(lib().ora_expected_utility(m, n, _p(F), _p(v), _p(lo), _p(hi), W.shape[0],
+                                            _p(W)))
 
 
 def num_threads():

@@ -96,6 +96,12 @@ int ora_generation(const ora_params *P, int problem, int m, int d, int64_t N, in
                    int32_t *parents_out, int32_t *surv_out, int *adapted);
 int ora_run(const ora_params *P, int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
             int gens, float *X, double *F, uint8_t *valid, double *V, double *V0, double *gamma);
+/* indicators.c: App. C.2 hypervolume (m = 2, 3; reference point ones on
+ * f' = (f - lo) / (hi - lo)) and the expected utility over a weight set */
+double ora_hypervolume(int m, int64_t n, const double *F, const uint8_t *valid, const double *lo,
+                       const double *hi);
+double ora_expected_utility(int m, int64_t n, const double *F, const uint8_t *valid,
+                            const double *lo, const double *hi, int64_t nw, const double *W);
 int ora_num_threads(void);
 void ora_set_num_threads(int n);
 
