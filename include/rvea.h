@@ -187,9 +187,13 @@ rvea_status rvea_set_state(rvea_run run, const float *X, const float *F,
                            const uint8_t *valid, const double *V, const double *gamma,
                            int64_t t);
 
-/* After rvea_step, before rvea_select: the offspring X (N x d float), their
- * objectives F (N x m float) and the mating pairs (ceil(N/2) x 2 slot
- * indices).  Any pointer may be NULL.  Waits for the stream. */
+/* The offspring X (N x d float), their objectives F (N x m float) and the
+ * mating pairs (ceil(N/2) x 2 slot indices) of the generation in progress
+ * (after rvea_step) or, between generations, of the last completed one
+ * (also after rvea_run_generations or a batch step; the next rvea_step
+ * reuses their rows).  RVEA_ESTATE when no generation has completed since
+ * creation, rvea_set_state or rvea_autotune.  Any pointer may be NULL.
+ * Waits for the stream. */
 rvea_status rvea_get_offspring(rvea_run run, float *X, float *F, int32_t *parents);
 
 /* After rvea_select: the ideal point (m float), the association of each
@@ -202,8 +206,8 @@ rvea_status rvea_get_selection(rvea_run run, float *zstar, int32_t *assoc, doubl
 /* Selected rows only: idx[0..n) are slot indices (offspring = 0) or
  * offspring indices (offspring = 1); writes their genes (n x d float) and
  * objectives (n x m float).  Either output may be NULL.  Valid between
- * generations (slots) or after rvea_step until the next rvea_step
- * (offspring).  Waits for the stream. */
+ * generations (slots) or whenever rvea_get_offspring is (offspring).
+ * Waits for the stream. */
 rvea_status rvea_get_rows(rvea_run run, int offspring, const int64_t *idx, int64_t n, float *X,
                           float *F);
 

@@ -659,9 +659,16 @@ rvea_status device_t(rvea_run r, int64_t *t)
     return RVEA_OK;
 }
 
-// the population whose merged buffer holds this generation's offspring:
-// the parents' (before rvea_select counts the generation, after it one less)
-int64_t offspring_pop(rvea_run r, int64_t td) { return r->phase == 2 ? td - 1 : td; }
+// the population whose merged buffer holds the offspring: after rvea_step
+// the parents' (the generation is not counted yet); after rvea_select, and
+// between generations for the last completed one, one less than the count
+int64_t offspring_pop(rvea_run r, int64_t td) { return r->phase == 1 ? td : td - 1; }
+
+// offspring are readable after rvea_step and, between generations, for the
+// last completed generation until the next step (their rows are only reused
+// by the next reproduction); not after set_state or an autotune, which
+// drew offspring without completing a generation
+bool offspring_readable(rvea_run r) { return r->phase != 0 || r->has_selection; }
 
 }  // namespace
 
@@ -733,7 +740,7 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
 rvea_status rvea_get_offspring(rvea_run r, float *X, float *F, int32_t *parents)
 {
     if (!r) return RVEA_EINVAL;
-    if (r->phase == 0) return RVEA_ESTATE;
+    if (!offspring_readable(r)) return RVEA_ESTATE;
     const RunView &R = r->R;
     HIPCHK(r, hipStreamSynchronize(active_stream(r)));
     if (X) {
@@ -783,7 +790,7 @@ rvea_status rvea_get_rows(rvea_run r, int offspring, const int64_t *idx, int64_t
                           float *F)
 {
     if (!r || (n > 0 && !idx) || n < 0) return RVEA_EINVAL;
-    if (offspring && r->phase == 0) return RVEA_ESTATE;
+    if (offspring && !offspring_readable(r)) return RVEA_ESTATE;
     const RunView &R = r->R;
     const int64_t lim = offspring ? R.N : R.K;
     for (int64_t q = 0; q < n; ++q)

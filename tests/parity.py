@@ -71,3 +71,77 @@ def survivor_near_ties(sg, so, apd_o, assoc_o, K):
         assert assoc_o[a] == j, f"vector {j}: GPU survivor {a} not in the subpopulation"
         assert abs(apd_o[a] - apd_o[b]) <= NEAR_TIE_RTOL * apd_o[b], f"vector {j} not a near-tie"
     return len(mism)
+
+
+def ora_params(O, prm):
+    """The oracle's parameter record for the binding's Params."""
+    return O.params(alpha=prm.alpha, fr=prm.fr, t_max=prm.t_max, eta_c=prm.eta_c,
+                    eta_m=prm.eta_m, p_c=prm.p_c, p_m=prm.p_m, lb=prm.lb, ub=prm.ub)
+
+
+def new_stats():
+    return dict(straddles=0, genes=0, near_ties=0, vectors=0, adaptations=0, generations=0)
+
+
+def check_generation(O, run, prm, st, off, sel, st2, stats, exact_survivors=False):
+    """One completed generation of `run` against the oracle, stage by stage
+    from identical state (Alg. 2): st is the run's state before it, off its
+    offspring (X, F, mating pairs), sel its selection, st2 its state after.
+
+    Mating draws exact; offspring genes bit-exact but for counted rounding
+    straddles (App. B); objectives at OBJ_RTOL; selection from the GPU's
+    merged objectives (Alg. 1): ideal point and association exact, APD at
+    APD_RTOL, survivors exact but for counted near-ties (none allowed with
+    exact_survivors); the new population is the survivors' rows; at an
+    adapting generation V exact and gamma at 1e-13."""
+    problem, m, d, N, K, seed = run.problem, run.m, run.d, run.N, run.K, run.seed
+    op = ora_params(O, prm)
+    period = O.adapt_period(prm.fr, prm.t_max)
+    t = st["t"] + 1
+    assert st2["t"] == t
+    parents, nv = O.mate(seed, t, st["valid"], N)
+    assert nv == st["valid"].sum()
+    assert np.array_equal(off["parents"], parents), f"mating differs at t={t}"
+    Xo, pre = O.reproduce(op, seed, t, st["X"], parents, N, with_pre=True)
+    stats["straddles"] += gene_mismatches(off["X"], Xo, pre)
+    stats["genes"] += Xo.size
+    objectives_close(off["F"], O.evaluate(problem, m, off["X"]))
+    Fm = np.vstack([st["F"], off["F"]]).astype(np.float64)
+    mv = np.concatenate([st["valid"], np.ones(N, np.uint8)])
+    ref = O.select(m, K, N, t, prm.t_max, prm.alpha, Fm, mv, st["V"], st["gamma"])
+    nt = compare_selection(sel, ref, K)
+    if exact_survivors:
+        assert nt == 0 and np.array_equal(sel["surv"], ref["surv"]), "survivors differ"
+    stats["near_ties"] += nt
+    stats["vectors"] += K
+    # the new population is the survivors' rows (Alg. 1)
+    Xm = np.vstack([st["X"], off["X"]])
+    s = sel["surv"]
+    assert np.array_equal(st2["valid"], (s >= 0).astype(np.uint8))
+    ok = s >= 0
+    assert np.array_equal(st2["X"][ok], Xm[s[ok]])
+    assert np.array_equal(st2["F"][ok], Fm[s[ok]].astype(np.float32))
+    if t % period == 0:
+        Vo, changed = O.adapt(st2["V0"], st2["F"].astype(np.float64), st2["valid"], st["V"])
+        assert np.array_equal(st2["V"], Vo), f"adapted vectors differ at t={t}"
+        if changed:
+            assert np.allclose(st2["gamma"], O.gamma(Vo), rtol=1e-13, atol=0)
+            stats["adaptations"] += 1
+    else:
+        assert np.array_equal(st2["V"], st["V"]) and np.array_equal(st2["gamma"], st["gamma"])
+    stats["generations"] += 1
+    return ref
+
+
+def lockstep(O, run, prm, gens, stats, exact_survivors=False):
+    """gens generations of a single run, each checked by check_generation;
+    the offspring are read between rvea_step and rvea_select."""
+    for _ in range(gens):
+        st = run.get_state()
+        run.step()
+        off = run.get_offspring()
+        run.select()
+        sel = run.get_selection()
+        run.adapt()
+        check_generation(O, run, prm, st, off, sel, run.get_state(), stats, exact_survivors)
+    return stats

@@ -1,13 +1,16 @@
-"""Batched runs: every run's result is the same alone and in the mix.
+"""Batched runs against the oracle, and alone == in the mix.
 
 Runs of different problems, objective counts, dimensions and sizes are
-advanced together by rvea_batch_step; each must end bit-identical to the same
-run advanced alone (single-run path, itself checked against the oracle in
-test_gpu_parity.py), also when runs join and leave at different generations
-and whether the batch replays captured graphs or launches eagerly.
+advanced together by rvea_batch_step.  Every batched generation of every run
+is compared with the oracle stage by stage from the run's state before the
+batch step (Alg. 2, Appendix B, Alg. 1, adaptation), while runs join and
+leave at different ticks, with captured graphs and with eager launches.  Each
+run must also end bit-identical to the same run advanced alone.
 """
 import numpy as np
 import pytest
+
+from parity import check_generation, new_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -33,9 +36,58 @@ def P():
     return P
 
 
+@pytest.fixture(scope="module")
+def O():
+    import oracle as O
+
+    O.lib()
+    return O
+
+
 def make(P, spec, t_max=30):
     problem, m, d, N, K, seed = spec
     return P.Run(problem, m, d, N, K, seed=seed, params=P.default_params(t_max=t_max))
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batched_generations_match_oracle(P, O, graphs):
+    """Each batched generation of each run equals the oracle's generation
+    from the run's state before the batch step; runs join at different ticks
+    and leave after different numbers of generations."""
+    prm = P.default_params(t_max=30)  # adaptation every 3 generations
+    runs = [make(P, s) for s in SPECS]
+    join_at = [0, 2, 0, 4, 1, 3]
+    gens = [10, 8, 11, 5, 9, 7]
+    batch = P.Batch(8)
+    batch.set_graphs(graphs)
+    stats = new_stats()
+    done = [0] * len(runs)
+    active = []
+    tick = 0
+    while any(done[i] < gens[i] for i in range(len(runs))):
+        for i in range(len(runs)):
+            if i not in active and done[i] == 0 and tick >= join_at[i]:
+                batch.admit(runs[i])
+                active.append(i)
+        before = {i: runs[i].get_state() for i in active}
+        batch.step()
+        for i in active:
+            r = runs[i]
+            check_generation(O, r, prm, before[i], r.get_offspring(), r.get_selection(),
+                             r.get_state(), stats)
+            done[i] += 1
+        for i in list(active):
+            if done[i] == gens[i]:
+                batch.retire(runs[i])
+                active.remove(i)
+        tick += 1
+    assert stats["generations"] == sum(gens)
+    assert stats["adaptations"] >= len(runs)
+    assert stats["straddles"] <= max(2, 1e-6 * stats["genes"]), stats
+    assert stats["near_ties"] <= max(1, 1e-4 * stats["vectors"]), stats
+    print(f"batched vs oracle (graphs={graphs}): {stats}")
+    for r in runs:
+        r.close()
 
 
 def same(a, b):
