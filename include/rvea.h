@@ -304,6 +304,43 @@ rvea_status rvea_batch_synchronize(rvea_batch batch);
 rvea_status rvea_batch_destroy(rvea_batch batch);
 const char *rvea_batch_last_error(rvea_batch batch);
 
+/* ------------------------------------------------------------- indicators
+ * Quality indicators of a set of objective rows, computed on the device.
+ *   F         device, n x m float, row-major
+ *   valid     device, n bytes (1 = the row counts) or NULL (every row counts);
+ *             a row with a non-finite objective never counts
+ *   lo, hi    host, m doubles each, finite, hi > lo: every objective is
+ *             normalised to f' = (f - lo) / (hi - lo) in binary64
+ *   out       device, one double, written when the enqueued work completes
+ *   workspace device, 256-byte aligned, at least rvea_indicator_footprint
+ *             bytes, owned by the caller, contents arbitrary on entry and
+ *             clobbered; it must not be reused until the work completes
+ * The work is enqueued on hip_stream (NULL = default stream); nothing waits.
+ * Argument errors return before anything is enqueued; launch errors return
+ * RVEA_EDEVICE with the text in rvea_last_error(NULL) on the same thread. */
+
+/* Workspace bytes for either indicator: n rows, nw weight rows
+ * (m in [2, 8], 0 <= n <= 2^24, 0 <= nw <= 2^24). */
+rvea_status rvea_indicator_footprint(int m, int64_t n, int64_t nw, size_t *bytes);
+
+/* Hypervolume of App. C.2: the volume of the union of the boxes [f', 1]
+ * (reference point: the vector of ones) over the counted rows whose f' lies
+ * strictly below 1 in every objective; m = 2 or 3, 0 <= n <= 2^18 (the work
+ * grows as n^2).  A sum of non-negative binary64 terms: relative error below
+ * about 4 n 2^-53.  n = 0 gives 0. */
+rvea_status rvea_hypervolume(int m, int64_t n, const float *F, const uint8_t *valid,
+                             const double *lo, const double *hi, double *out, void *workspace,
+                             size_t workspace_bytes, void *hip_stream);
+
+/* Expected utility over a weight set (the neuroevolution appendix's EU, for
+ * minimised objectives): the mean over the nw weight rows w of W (device,
+ * nw x m double, each equally likely) of the best utility -(w . f') over the
+ * counted rows; -inf when no row counts.  m in [2, 8], nw >= 1. */
+rvea_status rvea_expected_utility(int m, int64_t n, const float *F, const uint8_t *valid,
+                                  const double *lo, const double *hi, int64_t nw,
+                                  const double *W, double *out, void *workspace,
+                                  size_t workspace_bytes, void *hip_stream);
+
 const char *rvea_status_str(rvea_status s);
 const char *rvea_last_error(rvea_run run);
 

@@ -168,6 +168,16 @@ namespace {
 // message of the last failed rvea_create on this thread (no handle exists)
 thread_local char g_create_err[512] = "";
 
+}  // namespace
+
+// the thread's message for calls without a handle (rvea_create, indicators)
+void rvea::note_thread_error(const char *what, hipError_t e)
+{
+    std::snprintf(g_create_err, sizeof g_create_err, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+
 rvea_status fail(rvea_run r, hipError_t e, const char *what)
 {
     if (r) std::snprintf(r->err, sizeof r->err, "%s: %s", what, hipGetErrorString(e));

@@ -35,6 +35,7 @@ EXPORTS = [
     "rvea_batch_footprint", "rvea_batch_create", "rvea_batch_admit", "rvea_batch_retire",
     "rvea_batch_step", "rvea_batch_set_graphs", "rvea_batch_size", "rvea_batch_synchronize",
     "rvea_batch_destroy", "rvea_batch_last_error",
+    "rvea_indicator_footprint", "rvea_hypervolume", "rvea_expected_utility",
 ]
 
 
@@ -107,6 +108,14 @@ def _load():
         "rvea_batch_admit": [P, P], "rvea_batch_retire": [P, P], "rvea_batch_step": [P],
         "rvea_batch_set_graphs": [P, i32], "rvea_batch_size": [P, P],
         "rvea_batch_synchronize": [P], "rvea_batch_destroy": [P],
+    }.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    for name, args in {
+        "rvea_indicator_footprint": [i32, i64, i64, P],
+        "rvea_hypervolume": [i32, i64, P, P, P, P, P, P, sz, P],
+        "rvea_expected_utility": [i32, i64, P, P, P, P, i64, P, P, P, sz, P],
     }.items():
         fn = getattr(L, name)
         fn.argtypes = args
@@ -396,3 +405,78 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ indicators
+def indicator_footprint(m, n, nw=0):
+    b = C.c_size_t(0)
+    st = lib.rvea_indicator_footprint(m, n, nw, C.byref(b))
+    if st != RVEA_OK:
+        raise RveaError(st, "rvea_indicator_footprint: " + lib.rvea_status_str(st).decode())
+    return b.value
+
+
+def _device_rows(F, valid, device):
+    """F (n x m) and the optional valid mask as contiguous device tensors."""
+    F = torch.as_tensor(F, dtype=torch.float32, device=device).contiguous()
+    if F.ndim != 2:
+        raise ValueError("F must be n x m")
+    if valid is not None:
+        valid = torch.as_tensor(valid, dtype=torch.uint8, device=device).contiguous()
+        if valid.shape != (F.shape[0],):
+            raise ValueError("valid must have one entry per row")
+    return F, valid
+
+
+def _bounds(m, lo, hi):
+    lo = np.ascontiguousarray(np.zeros(m) if lo is None else lo, np.float64)
+    hi = np.ascontiguousarray(np.ones(m) if hi is None else hi, np.float64)
+    if lo.shape != (m,) or hi.shape != (m,):
+        raise ValueError("lo and hi need one value per objective")
+    return lo, hi
+
+
+def _indicator_call(fn, name, args, device, stream):
+    dev = torch.device(device)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        st = fn(*args(out, s))
+    if st != RVEA_OK:
+        raise RveaError(st, f"{name}: {lib.rvea_status_str(st).decode()} "
+                            f"{lib.rvea_last_error(None).decode()}")
+    s.synchronize()
+    return float(out.item())
+
+
+def hypervolume(F, valid=None, lo=None, hi=None, device="cuda:0", stream=None):
+    """Hypervolume of the rows of F (m = 2, 3) on normalised objectives
+    (F - lo) / (hi - lo), reference point ones (rvea_hypervolume)."""
+    F, valid = _device_rows(F, valid, device)
+    n, m = F.shape
+    lo, hi = _bounds(m, lo, hi)
+    ws = torch.empty(indicator_footprint(m, n) + 256, dtype=torch.uint8, device=F.device)
+    wsp = (ws.data_ptr() + 255) // 256 * 256
+    return _indicator_call(lib.rvea_hypervolume, "rvea_hypervolume", lambda out, s: (
+        m, n, C.c_void_p(F.data_ptr()), C.c_void_p(valid.data_ptr()) if valid is not None
+        else None, _p(lo), _p(hi), C.c_void_p(out.data_ptr()), C.c_void_p(wsp),
+        ws.numel() - (wsp - ws.data_ptr()), C.c_void_p(s.cuda_stream)), device, stream)
+
+
+def expected_utility(F, W, valid=None, lo=None, hi=None, device="cuda:0", stream=None):
+    """Mean over the weight rows W of the best utility -w . f' over the rows of
+    F (rvea_expected_utility)."""
+    F, valid = _device_rows(F, valid, device)
+    n, m = F.shape
+    W = torch.as_tensor(W, dtype=torch.float64, device=F.device).contiguous()
+    if W.ndim != 2 or W.shape[1] != m:
+        raise ValueError("W must be nw x m")
+    nw = W.shape[0]
+    lo, hi = _bounds(m, lo, hi)
+    ws = torch.empty(indicator_footprint(m, n, nw) + 256, dtype=torch.uint8, device=F.device)
+    wsp = (ws.data_ptr() + 255) // 256 * 256
+    return _indicator_call(lib.rvea_expected_utility, "rvea_expected_utility", lambda out, s: (
+        m, n, C.c_void_p(F.data_ptr()), C.c_void_p(valid.data_ptr()) if valid is not None
+        else None, _p(lo), _p(hi), nw, C.c_void_p(W.data_ptr()), C.c_void_p(out.data_ptr()),
+        C.c_void_p(wsp), ws.numel() - (wsp - ws.data_ptr()), C.c_void_p(s.cuda_stream)),
+        device, stream)
