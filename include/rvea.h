@@ -332,6 +332,20 @@ rvea_status rvea_hypervolume(int m, int64_t n, const float *F, const uint8_t *va
                              const double *lo, const double *hi, double *out, void *workspace,
                              size_t workspace_bytes, void *hip_stream);
 
+/* rvea_hypervolume for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument, and no device memory is allocated or
+ * freed.  Its working memory is a static 8 MiB array of the library on each
+ * GPU it runs on (kept until the process ends), so n may be at most 131,072
+ * (RVEA_ENOMEM beyond, with the reason in rvea_last_error(NULL)).  Every call
+ * on one GPU uses that GPU's array: calls that overlap on one GPU (different
+ * streams, different threads) race and must be serialised by the caller;
+ * consecutive calls on one stream are safe.  Same arguments, result and
+ * errors as rvea_hypervolume otherwise. */
+rvea_status rvea_hypervolume_noalloc(int m, int64_t n, const float *F, const uint8_t *valid,
+                                     const double *lo, const double *hi, double *out,
+                                     void *hip_stream);
+
 /* Expected utility over a weight set (the neuroevolution appendix's EU, for
  * minimised objectives): the mean over the nw weight rows w of W (device,
  * nw x m double, each equally likely) of the best utility -(w . f') over the

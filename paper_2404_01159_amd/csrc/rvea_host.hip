@@ -176,6 +176,11 @@ void rvea::note_thread_error(const char *what, hipError_t e)
     std::snprintf(g_create_err, sizeof g_create_err, "%s: %s", what, hipGetErrorString(e));
 }
 
+void rvea::note_thread_message(const char *msg)
+{
+    std::snprintf(g_create_err, sizeof g_create_err, "%s", msg);
+}
+
 namespace {
 
 rvea_status fail(rvea_run r, hipError_t e, const char *what)

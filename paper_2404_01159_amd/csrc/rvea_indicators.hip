@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "rvea.h"
 #include "rvea_internal.h"
@@ -243,6 +244,39 @@ __global__ __launch_bounds__(256) void k_eu_best(const float *F, const uint8_t *
     if (lane == 0) best[w] = b;
 }
 
+// Scratch of rvea_hypervolume_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends; room for kNoAllocRows rows.  Host
+// code must never pass `scratch` itself to a kernel (in host code the name
+// stands for a host-side symbol, not a device address): its device address
+// is looked up once per device and kept in g_scratch.
+constexpr int64_t kNoAllocRows = (int64_t)1 << 17;
+constexpr size_t kScratchBytes = 7 * ((size_t)kNoAllocRows * 8) + 2 * ((size_t)kNoAllocRows * 4);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// device address of the current device's scratch (looked up on the first
+// call on that device, with that device current)
+hipError_t scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
 rvea_status norm_of(int m, const double *lo, const double *hi, Norm *nm)
 {
     if (!lo || !hi) return RVEA_EINVAL;
@@ -328,6 +362,27 @@ rvea_status rvea_expected_utility(int m, int64_t n, const float *F, const uint8_
                        out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RVEA_OK : device_error("expected-utility launch", e);
+}
+
+rvea_status rvea_hypervolume_noalloc(int m, int64_t n, const float *F, const uint8_t *valid,
+                                     const double *lo, const double *hi, double *out,
+                                     void *hip_stream)
+{
+    if (m < 2 || m > 3 || n < 0 || !out || (n > 0 && !F)) return RVEA_EINVAL;
+    if (n > kNoAllocRows) {
+        rvea::note_thread_message("rvea_hypervolume_noalloc: more rows than its static "
+                                  "scratch holds (at most 131072)");
+        return RVEA_ENOMEM;
+    }
+    Norm nm;
+    rvea_status st = norm_of(m, lo, hi, &nm);
+    if (st != RVEA_OK) return st;
+    void *ws = nullptr;
+    hipError_t e = scratch_of_current_device(&ws);
+    if (e != hipSuccess) return device_error("hipGetSymbolAddress(scratch)", e);
+    if (hv_bytes(n) > kScratchBytes) return RVEA_ENOMEM;
+    e = enqueue_hv(F, valid, n, nm, out, ws, (hipStream_t)hip_stream);
+    return e == hipSuccess ? RVEA_OK : device_error("hypervolume launch", e);
 }
 
 }  // extern "C"

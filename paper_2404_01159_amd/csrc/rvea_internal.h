@@ -12,6 +12,7 @@ namespace rvea {
 // records the HIP error of a call that has no run handle; read back with
 // rvea_last_error(NULL) on the same thread
 void note_thread_error(const char *what, hipError_t e);
+void note_thread_message(const char *msg);
 
 int pick_segment(int d);                 // lanes per individual (initialization)
 int offspring_segment(int d, int64_t N);  // lanes per parent pair

@@ -36,6 +36,7 @@ EXPORTS = [
     "rvea_batch_step", "rvea_batch_set_graphs", "rvea_batch_size", "rvea_batch_synchronize",
     "rvea_batch_destroy", "rvea_batch_last_error",
     "rvea_indicator_footprint", "rvea_hypervolume", "rvea_expected_utility",
+    "rvea_hypervolume_noalloc",
 ]
 
 
@@ -116,6 +117,7 @@ def _load():
         "rvea_indicator_footprint": [i32, i64, i64, P],
         "rvea_hypervolume": [i32, i64, P, P, P, P, P, P, sz, P],
         "rvea_expected_utility": [i32, i64, P, P, P, P, i64, P, P, P, sz, P],
+        "rvea_hypervolume_noalloc": [i32, i64, P, P, P, P, P, P],
     }.items():
         fn = getattr(L, name)
         fn.argtypes = args
