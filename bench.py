@@ -37,11 +37,67 @@ def kernel_work(name, run):
         # read both parent rows of every pair, write every child row and its objectives
         return "bytes", 2 * P * d * 4 + N * d * 4 + N * m * 4
     if name == "assoc":
-        # every (merged row, vector) pair: m multiplies, m-1 adds, 1 max
-        return "flops", (K + N) * K * 2 * m
+        # every (merged row, vector) pair: an m-term dot product (m fused
+        # multiply-adds, 2m flops) and one max
+        return "flops", (K + N) * K * (2 * m + 1)
     if name == "rerank":
         return "bytes", (K + N) * (m * 4 + 8 + 4)
     return "bytes", 0
+
+
+def roofline_of(name, run, avg_ms, launches, traffic=None):
+    """Roofline record of one kernel from its per-launch time."""
+    unit, work = kernel_work(name, run)
+    if unit == "bytes":
+        ach = work / (avg_ms * 1e-3) / 1e9
+        return dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=ach / PEAK_HBM_GBS, traffic=traffic, kernel=name,
+                    avg_launch_us=avg_ms * 1e3, launches=launches, algorithmic_bytes=work)
+    ach = work / (avg_ms * 1e-3) / 1e12
+    return dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=ach / PEAK_FP32_TFLOPS, traffic=None, kernel=name,
+                avg_launch_us=avg_ms * 1e3, launches=launches, algorithmic_flops=work)
+
+
+def sweeps_leg(a):
+    """The paper's two scaling sweeps (its Tables 3 and 4): Series 1 (m = 3,
+    d = 100, n = 2^5..2^14) and Series 2 (n = 100, d = 2^9..2^18), 100
+    generations each on the linear-front multimodal problem; per point the
+    time per generation (graph-replayed run) and the reproduction and
+    association kernels against their rooflines."""
+    import torch
+
+    import paper_2404_01159_amd as P
+    from workloads import SERIES1, SERIES2
+
+    pts = []
+    for c in SERIES1 + SERIES2:
+        prm = P.default_params(t_max=c["gens"])
+        run = P.Run(c["problem"], c["m"], c["d"], c["N"], c["K"], seed=c["seed"], params=prm)
+        run.prepare(c["gens"])
+        run.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.run(c["gens"])
+        run.synchronize()
+        el = time.perf_counter() - t0
+        run.step()
+        t = run.time_kernels(TIMING_REPS)
+        run.select()
+        run.adapt()
+        run.synchronize()
+        off = roofline_of("offspring", run, t["offspring"], TIMING_REPS)
+        asc = roofline_of("assoc", run, t["assoc"], TIMING_REPS)
+        run.close()
+        pts.append(dict(workload=c["name"], series=c["series"], n=c["n"], d=c["d"], N=c["N"],
+                        K=c["K"], ms_per_generation=el * 1e3 / c["gens"],
+                        generations_per_s=c["gens"] / el,
+                        offspring_us=off["avg_launch_us"], offspring_hbm_frac=off["frac"],
+                        assoc_us=asc["avg_launch_us"], assoc_fp32_frac=asc["frac"],
+                        rerank_us=t["rerank"] * 1e3))
+    return dict(workload="Series 1: m=3, d=100, n=2^5..2^14; Series 2: m=3, n=100, "
+                         "d=2^9..2^18; N=n, K=the smallest lattice count >= n, 100 generations",
+                points=pts)
 
 
 def measured_traffic(kernel):
@@ -83,8 +139,11 @@ def cpu_baseline(cfg, budget_s):
 
 def policy_flops(N, E, T):
     """Algorithmic flops of one rollout launch: the three policy products
-    (64x32, 64x64, 8x64 per rollout step) and the dynamics A x + B u."""
-    per_step = 2 * (64 * 32 + 64 * 64 + 8 * 64) + 2 * (32 * 32 + 32 * 8)
+    (64x32, 64x64, 8x64 per rollout step, on the matrix cores in bfloat16).
+    The dynamics A x + B u (2 (32x32 + 32x8) flops per step) are not
+    counted: their split-bfloat16 products are extra matrix work of the
+    implementation, not of the policy."""
+    per_step = 2 * (64 * 32 + 64 * 64 + 8 * 64)
     return N * E * T * per_step
 
 
@@ -106,6 +165,7 @@ def policy_leg(a):
     warm.synchronize()
     warm.close()
     run = mk(C["seed"])
+    st0 = run.get_state(genes=False)
     tuning = run.autotune() if not a.no_autotune else None
     run.prepare(C["gens"])
     run.synchronize()
@@ -115,11 +175,23 @@ def policy_leg(a):
     run.synchronize()
     el = time.perf_counter() - t0
     counters = run.counters()
+    st = run.get_state(genes=False)
     run.close()
     out = {"workload": "4,096 policies 32-64-64-8 tanh (d=6,728), m=2, K=4,096, 16 rollouts "
                        "x 200 steps, 50 generations",
            "generations_per_s": C["gens"] / el, "ms_per_generation": el * 1e3 / C["gens"],
            "counters": counters, "assoc_tiles": tuning}
+    # quality of the final survivors: objectives normalised by lo = 0 and
+    # hi = the initial population's largest values (both objectives are sums
+    # of squares), hypervolume with reference point ones and expected utility
+    # over 100 evenly spread weights
+    hi = st0["F"][st0["valid"] == 1].astype("float64").max(axis=0)
+    W = weights_simplex(2, 99)
+    out["indicators"] = dict(
+        normalisation="lo = 0, hi = the initial population's largest objective values",
+        hypervolume_initial=P.hypervolume(st0["F"], st0["valid"], [0.0, 0.0], hi),
+        hypervolume_final=P.hypervolume(st["F"], st["valid"], [0.0, 0.0], hi),
+        expected_utility_final=P.expected_utility(st["F"], W, st["valid"], [0.0, 0.0], hi))
     names = ["offspring", "assoc", "rerank", "adapt", "rollout"]
     run = mk(C["seed"])
     if not a.no_autotune:
@@ -150,6 +222,66 @@ def policy_leg(a):
         out["cpu_baseline"] = dict(value=1.0 / el, unit="generations/s", cores=O.num_threads(),
                                    kind="oracle", sample=f"generation 1 of the same workload, "
                                                          f"{el:.1f} s")
+    return out
+
+
+def weights_simplex(m, H):
+    """Das-Dennis weight vectors on the simplex (entries a/H summing to 1),
+    each equally likely: the weight set of the expected utility."""
+    import itertools
+
+    import numpy as np
+
+    rows = []
+    for c in itertools.combinations(range(1, H + m), m - 1):
+        prev, a = 0, []
+        for ci in c:
+            a.append(ci - prev - 1)
+            prev = ci
+        a.append(H + m - 1 - prev)
+        rows.append(a)
+    return np.array(rows, np.float64) / H
+
+
+def indicators_leg(a):
+    """Hypervolume (App. C.2) and expected utility of the 105-vector
+    workload's final survivors (sphere-front problem, whose front spans
+    [0, 1] in every objective: no normalisation), and the time of the
+    device hypervolume on the 10,011-vector workload's final population."""
+    import torch
+
+    import paper_2404_01159_amd as P
+    from workloads import CONFIGS
+
+    out = {}
+    c = CONFIGS["small_m3_d12_n105"]
+    run = P.Run(c["problem"], c["m"], c["d"], c["N"], c["K"], seed=c["seed"],
+                params=P.default_params(t_max=c["gens"]))
+    run.run(c["gens"])
+    st = run.get_state(genes=False)
+    run.close()
+    out["small_m3_d12_n105"] = dict(
+        generations=c["gens"], hypervolume=P.hypervolume(st["F"], st["valid"]),
+        expected_utility=P.expected_utility(st["F"], weights_simplex(3, 13), st["valid"]))
+    c = CONFIGS[WORKLOAD]
+    run = P.Run(c["problem"], c["m"], c["d"], c["N"], c["K"], seed=c["seed"],
+                params=P.default_params(t_max=c["gens"]))
+    run.run(c["gens"])
+    st = run.get_state(genes=False)
+    run.close()
+    F = torch.from_numpy(st["F"]).cuda()
+    v = torch.from_numpy(st["valid"]).cuda()
+    hi = 1.1 * st["F"][st["valid"] == 1].astype("float64").max(axis=0)
+    lo = [0.0] * c["m"]
+    P.hypervolume(F, v, lo, hi)  # warm
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hv = P.hypervolume(F, v, lo, hi)
+    el = (time.perf_counter() - t0) / reps
+    out[WORKLOAD] = dict(generations=c["gens"], rows=c["K"], hypervolume=hv,
+                         normalisation="lo = 0, hi = 1.1 x the survivors' largest values",
+                         hypervolume_call_ms=el * 1e3)
     return out
 
 
@@ -217,6 +349,10 @@ def main():
                     help="keep the default association tiles")
     ap.add_argument("--no-policy", action="store_true",
                     help="skip the policy-rollout (neuroevolution-shaped) workload")
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the population-size and dimension sweeps")
+    ap.add_argument("--no-indicators", action="store_true",
+                    help="skip the hypervolume / expected-utility leg")
     ap.add_argument("--serve-runs", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
@@ -279,6 +415,7 @@ def main():
     # stream (a replayed graph cannot carry fresh events, and an event pair
     # around every single launch adds its own dispatch time)
     roof = None
+    rooflines = {}
     per_kernel = {}
     if not a.no_timing:
         run.step()
@@ -289,20 +426,11 @@ def main():
         for k in ("offspring", "assoc", "rerank"):
             per_kernel[k] = (t[k], TIMING_REPS)
         dom = max(per_kernel, key=lambda k: per_kernel[k][0])
-        avg_ms, n = per_kernel[dom]
-        unit, work = kernel_work(dom, run)
-        if unit == "bytes":
-            ach = work / (avg_ms * 1e-3) / 1e9
-            roof = dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s",
-                        frac=ach / PEAK_HBM_GBS,
-                        traffic=measured_traffic(dom) if a.config == WORKLOAD else None,
-                        kernel=dom, avg_launch_us=avg_ms * 1e3, launches=n,
-                        algorithmic_bytes=work)
-        else:
-            ach = work / (avg_ms * 1e-3) / 1e12
-            roof = dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                        frac=ach / PEAK_FP32_TFLOPS, traffic=None, kernel=dom,
-                        avg_launch_us=avg_ms * 1e3, launches=n, algorithmic_flops=work)
+        for k in ("offspring", "assoc"):
+            avg_ms, n = per_kernel[k]
+            traffic = measured_traffic(k) if (a.config == WORKLOAD and k == "offspring") else None
+            rooflines[k] = roofline_of(k, run, avg_ms, n, traffic)
+        roof = rooflines.get(dom) or roofline_of(dom, run, *per_kernel[dom])
     run.close()
 
     serving = None
@@ -312,6 +440,14 @@ def main():
     policy = None
     if not a.no_policy:
         policy = policy_leg(a)
+
+    sweeps = None
+    if not a.no_sweeps:
+        sweeps = sweeps_leg(a)
+
+    indicators = None
+    if not a.no_indicators:
+        indicators = indicators_leg(a)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -334,12 +470,15 @@ def main():
                    "N": cfg["N"], "K": cfg["K"], "m": cfg["m"], "d": cfg["d"],
                    "generations_timed": a.steps, "survivors_final": int(st["valid"].sum())},
         "roofline": roof,
+        "rooflines": rooflines,
         "kernels_avg_us": {k: v[0] * 1e3 for k, v in per_kernel.items()},
         "assoc_tiles": tuning,
         "counters": counters,
         "cpu_baseline": cpu,
         "serving": serving,
         "policy": policy,
+        "sweeps": sweeps,
+        "indicators": indicators,
     }
     print(json.dumps(out), flush=True)
 

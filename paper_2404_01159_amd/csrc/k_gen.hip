@@ -439,7 +439,11 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
 
     const int seg = threadIdx.x / S, lane = threadIdx.x % S;
     const int64_t P = (R.N + 1) / 2;
-    const int64_t p = bx * SEGS + seg;
+    // segment u of the grid: pair p, part sp of its genes (osplit parts)
+    const int ns = R.osplit;
+    const int64_t u = bx * SEGS + seg;
+    const int64_t p = ns == 1 ? u : u / ns;
+    const int sp = ns == 1 ? 0 : (int)(u - p * ns);
     const bool active = p < P;
     const int64_t pop = *R.t_done;  // the parents' population
     const uint32_t t = (uint32_t)(pop + 1);
@@ -448,7 +452,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     const bool has2 = o2 < R.N;
     const uint32_t nv = (uint32_t)*R.nvalid;
     if (nv == 0) {  // no parent left (every row was non-finite): offspring are empty
-        if (active && lane == 0) {
+        if (active && lane == 0 && sp == 0) {
             for (int k = 0; k < R.m; ++k) {
                 Fm[(R.K + o1) * R.m + k] = __int_as_float(0x7fc00000);
                 if (has2) Fm[(R.K + o2) * R.m + k] = __int_as_float(0x7fc00000);
@@ -497,6 +501,9 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         float *c1row = R.X + (int64_t)orow1 * R.ld;
         float *c2row = has2 ? R.X + (int64_t)orow2 * R.ld : nullptr;
         const int Q = (R.d + 3) / 4;
+        // this segment's quads: part sp of ns contiguous parts
+        const int qn = ns == 1 ? Q : (Q + ns - 1) / ns;
+        const int qa = sp * qn, qb = qa + qn < Q ? qa + qn : Q;
         const double lb = R.lb, ub = R.ub;
         const double np1 = R.eta_c + 1.0;
         const int nroot =
@@ -516,7 +523,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         int p1 = 0, p2 = 0;
         int nx1 = n1 > 0 ? st1[0] : INT_MAX, nx2 = n2 > 0 ? st2[0] : INT_MAX;
 
-        for (int q = lane; q < Q; q += S) {
+        for (int q = qa + lane; q < qb; q += S) {
             const float4 xa = *reinterpret_cast<const float4 *>(x1row + 4 * q);
             const float4 xb = *reinterpret_cast<const float4 *>(x2row + 4 * q);
             const float pa[4] = {xa.x, xa.y, xa.z, xa.w};
@@ -600,13 +607,25 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         }
         g1 = seg_sum<S>(g1);
         g2 = seg_sum<S>(g2);
+        // a pair split over segments: each stores its partial sums, which
+        // the finishing kernel adds in part order (kernel order makes them
+        // visible) to form the pair's objectives
+        bool fin = true;
+        if (evaluate && ns > 1) {
+            if (lane == 0) {
+                double *gp = R.gpart + (p * ns + sp) * 2;
+                gp[0] = g1;
+                gp[1] = g2;
+            }
+            fin = false;
+        }
         float pos1[kMaxM], pos2[kMaxM];
 #pragma unroll
         for (int k = 0; k < kMaxM - 1; ++k) {
             pos1[k] = __shfl(pv1[k & 3], k >> 2, S);
             pos2[k] = __shfl(pv2[k & 3], k >> 2, S);
         }
-        if (evaluate && (lane == 0 || (lane == 1 && has2))) {
+        if (evaluate && fin && (lane == 0 || (lane == 1 && has2))) {
             // objectives, child 1 on lane 0 and child 2 on lane 1 (two lanes
             // finish them side by side); rows that take part (finite F) and
             // their LDS minima
@@ -651,7 +670,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     }
     // the parents' slots (kept for the host): stored last, so that no wait
     // for an earlier load also waits for this store
-    if (active && lane == 0) {
+    if (active && lane == 0 && sp == 0) {
         R.parents[2 * p] = a;
         R.parents[2 * p + 1] = b;
     }
@@ -668,6 +687,44 @@ __global__ __launch_bounds__(kOffBlock) void k_offspring(RunView R)
     offspring_body<S, NR, DK, kOffBlock>(R, blockIdx.x);
 }
 
+// Objectives of the children of pairs split over segments (osplit > 1),
+// one lane per child: the parts' distance sums added in part order, the
+// position genes read back from the child's row; then, as in the offspring
+// kernel, the row's take-part flag, the non-finite count and the children's
+// share of the ideal point.
+__device__ __forceinline__ void offspring_finish_body(const RunView &R, int64_t bx)
+{
+    const int64_t o = bx * 256 + threadIdx.x;
+    const int64_t P = (R.N + 1) / 2;
+    const int64_t pop = *R.t_done;
+    if (*R.nvalid == 0) return;  // no parent: the offspring kernel left empty children
+    float *Fm = fm_of(R, pop);
+    const bool has = o < R.N;
+    float f[kMaxM] = {};
+    if (has) {
+        const int64_t p = o < P ? o : o - P;
+        const int c = o < P ? 0 : 1;
+        const int ns = R.osplit;
+        double g = 0.0;
+        for (int k = 0; k < ns; ++k) g += R.gpart[(p * ns + k) * 2 + c];
+        const float *row = R.X + (int64_t)R.off_row[o] * R.ld;
+        float pos[kMaxM];
+#pragma unroll
+        for (int k = 0; k < kMaxM - 1; ++k) pos[k] = k < R.m - 1 ? row[k] : 0.f;
+        pos[kMaxM - 1] = 0.f;
+        finish_objectives(R.problem, R.m, R.d, pos, g, f);
+#pragma unroll
+        for (int k = 0; k < kMaxM; ++k)
+            if (k < R.m) Fm[(R.K + o) * R.m + k] = f[k];
+    }
+    child_ideal(R, pop + 1, has, R.K + o, f);
+}
+
+__global__ __launch_bounds__(256) void k_offspring_finish(RunView R)
+{
+    offspring_finish_body(R, blockIdx.x);
+}
+
 // ----------------------------------------------------- batched (many runs)
 __global__ __launch_bounds__(256) void kb_prep(const RunView *runs, const Span *sp, int n)
 {
@@ -679,6 +736,12 @@ __global__ __launch_bounds__(kBlock) void kb_offspring(const RunView *runs, cons
 {
     const int s = find_span(sp, n, blockIdx.x);
     offspring_body<S, 0, -1, kBlock>(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+__global__ __launch_bounds__(256) void kb_offspring_finish(const RunView *runs, const Span *sp,
+                                                           int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    offspring_finish_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 
 // ------------------------------------------------------------- launchers
@@ -704,6 +767,25 @@ int offspring_segment(int d, int64_t N)
     const int64_t P = (N + 1) / 2;
     if (S == 64 && P > kResidentOffspringWaves && P <= 2 * kResidentOffspringWaves) return 32;
     return S;
+}
+
+// Few pairs of long rows (fewer pairs than the resident wavefronts, rows of
+// at least two 64-lane passes): each pair's genes are split into contiguous
+// parts, one 64-lane segment each, enough to fill the resident wavefronts,
+// each part at least two quads per lane.  A function of d and N only, so
+// that results (the order of the distance sums) do not depend on the device
+// or on whether the run is batched.
+int offspring_splits(int d, int64_t N)
+{
+    const int S = offspring_segment(d, N);
+    const int64_t P = (N + 1) / 2;
+    const int64_t Q = (d + 3) / 4;
+    if (S < 64 || P >= kResidentOffspringWaves) return 1;
+    int64_t ns = (kResidentOffspringWaves + P - 1) / P;
+    const int64_t most = Q / (2 * S);
+    if (ns > most) ns = most;
+    if (ns > 256) ns = 256;
+    return ns < 1 ? 1 : (int)ns;
 }
 
 #define RVEA_SEG_DISPATCH(S, KERNEL, GRID_UNITS, STREAM, VIEW)                                 \
@@ -738,6 +820,7 @@ hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span 
         default: kb_offspring<64><<<g, kBlock, 0, s>>>(runs, sp, n); break;
         }
         break;
+    case BP_OFFSPRING_FIN: kb_offspring_finish<<<g, 256, 0, s>>>(runs, sp, n); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -780,7 +863,7 @@ template <int NR, int DK>
 void launch_offspring_as(const RunView &R, hipStream_t s)
 {
     const int S = offspring_segment(R.d, R.N);
-    const int64_t P = (R.N + 1) / 2;
+    const int64_t P = (R.N + 1) / 2 * R.osplit;  // segments
     switch (S) {
     case 4: k_offspring<4, NR, DK><<<blocks_of(P, kOffBlock / 4), kOffBlock, 0, s>>>(R); break;
     case 8: k_offspring<8, NR, DK><<<blocks_of(P, kOffBlock / 8), kOffBlock, 0, s>>>(R); break;
@@ -804,6 +887,8 @@ hipError_t launch_offspring(const RunView &R, hipStream_t s)
     } else {
         launch_offspring_as<0, -1>(R, s);
     }
+    if (R.osplit > 1 && R.problem != kPolicy)
+        k_offspring_finish<<<(unsigned)((R.N + 255) / 256), 256, 0, s>>>(R);
     return hipGetLastError();
 }
 

@@ -166,8 +166,10 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
     case BP_PREP: return (R.K + R.N + 255) / 256;
     case BP_OFFSPRING: {
         const int S = offspring_segment(R.d, R.N);
-        return ((R.N + 1) / 2 + (kBlock / S) - 1) / (kBlock / S);
+        return ((R.N + 1) / 2 * R.osplit + (kBlock / S) - 1) / (kBlock / S);
     }
+    case BP_OFFSPRING_FIN:  // only runs whose pairs are split over segments
+        return R.osplit > 1 ? (R.N + 255) / 256 : 0;
     case BP_ASSOC:
     case BP_GAMMA_ASSOC: return batch_phase_nbx(phase, R) * R.KC;
     case BP_RERANK: return (R.M + rerank_rows_per_wave() - 1) / rerank_rows_per_wave();
@@ -181,7 +183,7 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
 hipError_t launch_batch(int phase, int cls, const RunView *runs, const Span *sp, int n,
                         int64_t blocks, hipStream_t s)
 {
-    if (phase <= BP_OFFSPRING) return launch_batch_gen(phase, cls, runs, sp, n, blocks, s);
+    if (phase <= BP_OFFSPRING_FIN) return launch_batch_gen(phase, cls, runs, sp, n, blocks, s);
     if (phase == BP_ADAPT) return launch_batch_vectors(phase, cls, runs, sp, n, blocks, s);
     return launch_batch_select(phase, cls, runs, sp, n, blocks, s);
 }

@@ -46,6 +46,8 @@ struct RunView {
     float *Fms;         // 2 x M x m merged objectives (slots, then offspring)
     uint8_t *mvalid;    // M: row takes part in the selection
     int32_t *parents;   // ceil(N/2) x 2 slot indices
+    int osplit;         // segments per parent pair in the offspring kernel (1: one)
+    double *gpart;      // ceil(N/2) x osplit x 2 partial distance sums (osplit > 1)
     int32_t *vs;        // K x 2: valid slots, ascending, each with its physical row
     int32_t *nvalid;    // 1
     int32_t *stamp;     // K+N: the generation that will read the row (rows of

@@ -23,7 +23,7 @@ constexpr int kKernels = 5;  // timed kernel ids: offspring, assoc, rerank, gamm
 constexpr int kLqFloats = 32 * 32 + 32 * 8 + kPolicyE * 32;  // A, B, x0 of the policy problem
 
 struct Layout {
-    int ld, stride, KC, CS;
+    int ld, stride, KC, CS, osplit;
     size_t off[40];
     size_t total;
 };
@@ -32,7 +32,7 @@ enum Buf {
     B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_MVALID, B_PARENTS, B_VS,
     B_NVALID, B_STAMP, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
     B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_BCOUNT, B_FREECNT, B_PEN,
-    B_NDONE, B_LQ, B_COUNT
+    B_NDONE, B_LQ, B_GPART, B_COUNT
 };
 
 int64_t binomial(int64_t n, int64_t k)
@@ -90,6 +90,7 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
     L.CS = (int)cs;
     L.KC = (int)((K + cs - 1) / cs);
     const int64_t P = (N + 1) / 2;
+    L.osplit = offspring_splits(d, N);
     const size_t sz[B_COUNT] = {
         (size_t)(K + N) * L.ld * 4, (size_t)2 * K * 4, (size_t)N * 4, (size_t)2 * K,
         (size_t)2 * M * m * 4, (size_t)M,
@@ -98,7 +99,8 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
         (size_t)2 * m * 4, (size_t)2 * m * 4, (size_t)L.KC * M * 4, (size_t)L.KC * M * 4,
         (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4,
         (size_t)((K + N + 255) / 256) * 4, 4, 8, 4,
-        problem == kPolicy ? (size_t)kLqFloats * 4 : 0};
+        problem == kPolicy ? (size_t)kLqFloats * 4 : 0,
+        L.osplit > 1 ? (size_t)P * L.osplit * 2 * 8 : 8};
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -379,6 +381,8 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.Fms = (float *)(w + L.off[B_FM]);
     R.mvalid = (uint8_t *)(w + L.off[B_MVALID]);
     R.parents = (int32_t *)(w + L.off[B_PARENTS]);
+    R.osplit = L.osplit;
+    R.gpart = (double *)(w + L.off[B_GPART]);
     R.vs = (int32_t *)(w + L.off[B_VS]);
     R.nvalid = (int32_t *)(w + L.off[B_NVALID]);
     R.stamp = (int32_t *)(w + L.off[B_STAMP]);

@@ -16,6 +16,7 @@ void note_thread_message(const char *msg);
 
 int pick_segment(int d);                 // lanes per individual (initialization)
 int offspring_segment(int d, int64_t N);  // lanes per parent pair
+int offspring_splits(int d, int64_t N);   // segments per parent pair
 int assoc_rows_per_block();
 int rerank_rows_per_wave();      // batched launch
 int default_rerank_rows(int64_t rows);  // single-run default for this many rows
@@ -41,7 +42,7 @@ hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring);
 // span table (runs of the same template class: segment width for the
 // offspring, objective count for the association phases).
 enum BatchPhase {
-    BP_PREP, BP_OFFSPRING, BP_ASSOC, BP_RERANK,
+    BP_PREP, BP_OFFSPRING, BP_OFFSPRING_FIN, BP_ASSOC, BP_RERANK,
     BP_NEWPOP, BP_ADAPT, BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
 int batch_phase_class(int phase, const RunView &R);       // template class of a run

@@ -24,6 +24,7 @@ SPECS = [
     (1, 8, 300, 120, 120, 4),
     (2, 3, 700, 300, 300, 5),
     (3, 3, 12, 91, 91, 6),
+    (1, 3, 2048, 100, 105, 7),  # long rows, few pairs: each pair split over segments
 ]
 
 
@@ -56,8 +57,8 @@ def test_batched_generations_match_oracle(P, O, graphs):
     and leave after different numbers of generations."""
     prm = P.default_params(t_max=30)  # adaptation every 3 generations
     runs = [make(P, s) for s in SPECS]
-    join_at = [0, 2, 0, 4, 1, 3]
-    gens = [10, 8, 11, 5, 9, 7]
+    join_at = [0, 2, 0, 4, 1, 3, 2]
+    gens = [10, 8, 11, 5, 9, 7, 6]
     batch = P.Batch(8)
     batch.set_graphs(graphs)
     stats = new_stats()
@@ -120,12 +121,12 @@ def test_staggered_join_and_leave(P):
     path continues them afterwards."""
     alone = [make(P, s) for s in SPECS]
     mixed = [make(P, s) for s in SPECS]
-    gens = [20, 15, 25, 9, 17, 12]
+    gens = [20, 15, 25, 9, 17, 12, 10]
     for r, g in zip(alone, gens):
         r.run(g)
     batch = P.Batch(8)
     done = [0] * len(SPECS)
-    join_at = [0, 3, 0, 5, 1, 8]
+    join_at = [0, 3, 0, 5, 1, 8, 2]
     tick = 0
     active = set()
     while any(done[i] < gens[i] for i in range(len(SPECS))):

@@ -69,6 +69,7 @@ LOCKSTEP_CASES = [
     (1, 5, 33, 126, 126, 7, 12),
     (2, 8, 17, 120, 120, 9, 12),
     (3, 3, 1001, 91, 91, 2, 12),
+    (2, 3, 4000, 60, 66, 4, 11),  # long rows, few pairs: each pair split over segments
 ]
 
 

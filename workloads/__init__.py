@@ -32,6 +32,35 @@ CONFIGS = {
                                  K=100128, gens=50, seed=0),
 }
 
+# The paper's two scaling sweeps (its Tables 3 and 4, DTLZ1, m = 3, 100
+# generations), each point a population size n and a dimension d.  Reading:
+# the population is N = n individuals and the reference vectors are the
+# smallest Das-Dennis lattice with at least n of them (K >= N, so every
+# initial individual has a slot; empty slots take no part).
+#   Series 1: d = 100, n = 2^5 .. 2^14;  Series 2: n = 100, d = 2^9 .. 2^18.
+def lattice_count(H, m):
+    from math import comb
+
+    return comb(H + m - 1, m - 1)
+
+
+def smallest_lattice_at_least(n, m):
+    """(H, K): the fewest divisions H whose lattice count K = C(H+m-1, m-1) >= n."""
+    H = 1
+    while lattice_count(H, m) < n:
+        H += 1
+    return H, lattice_count(H, m)
+
+
+def sweep_point(series, n, d, m=3, gens=100, seed=0):
+    H, K = smallest_lattice_at_least(n, m)
+    return dict(name=f"series{series}_m{m}_d{d}_n{n}", series=series, problem=LINEAR_MULTIMODAL,
+                m=m, d=d, n=n, N=n, K=K, H=H, gens=gens, seed=seed)
+
+
+SERIES1 = [sweep_point(1, 2 ** e, 100) for e in range(5, 15)]
+SERIES2 = [sweep_point(2, 100, 2 ** e) for e in range(9, 19)]
+
 # Neuroevolution-shaped workload: N = 4,096 policies (32 -> 64 -> 64 -> 8 tanh,
 # d = 6,728 weights, second hidden layer without bias), m = 2, K = N (H = 4,095),
 # E = 16 rollouts of T = 200 steps on the linear system of ``lq_system``.
@@ -105,12 +134,6 @@ def seeds(n, base=0):
 # {2,3,5,8}, d uniform in [30, 2000] and the lattice divisions H uniformly
 # over the values whose count C(H+m-1, m-1) lies in [100, 10011]; N = K.
 SERVE_H_RANGE = {2: (99, 10010), 3: (13, 140), 5: (5, 19), 8: (3, 8)}
-
-
-def lattice_count(H, m):
-    from math import comb
-
-    return comb(H + m - 1, m - 1)
 
 
 def serving_specs(n=256, rate=20.0, seed=0, gens=100):
