@@ -434,6 +434,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     constexpr int SEGS = BS / S;
     __shared__ int32_t sh_sites[SEGS][2][kMaxSites];
     __shared__ double sh_mags[SEGS][2][kMaxSites];
+    __shared__ float sh_vals[SEGS][2][kMaxSites];  // mutated gene at each site
     __shared__ uint32_t szmin[kMaxM];
     if (threadIdx.x < kMaxM) szmin[threadIdx.x] = 0xffffffffu;
 
@@ -515,11 +516,39 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         double g1 = 0.0, g2 = 0.0;
         float pv1[4] = {0.f, 0.f, 0.f, 0.f}, pv2[4] = {0.f, 0.f, 0.f, 0.f};
 
+        // the pair's mutation sites in this segment's genes, one lane per
+        // site and both children at once: the site's SBX child (the binary64
+        // steps of the streaming loop below, from the same Philox word) and
+        // its polynomial mutation, kept as the final binary32 gene, so the
+        // loop only substitutes them
+        const int nsites = n1 + n2;
+        for (int b0 = 0; b0 < nsites; b0 += S) {  // uniform per segment
+            const int idx = b0 + lane;
+            const int c = idx < n1 ? 0 : 1;
+            const int k = c ? idx - n1 : idx;
+            const int g = idx < nsites ? sh_sites[seg][c][k] : -1;
+            if (g >= 4 * qa && g < 4 * qb) {
+                const W4 w = draw(R, (uint32_t)(g >> 2), (uint32_t)p, t, TAG_SBX);
+                const int kk = g & 3;
+                const uint32_t word = kk == 0 ? w.w[0] : kk == 1 ? w.w[1] : kk == 2 ? w.w[2] : w.w[3];
+                const double xa_ = (double)x1row[g], xb_ = (double)x2row[g];
+                const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
+                double B = sgn * sbx_beta<NR>(unif24(word), R.eta_c, nroot);
+                if (((word >> 6) & 1u) || nocross) B = 1.0;
+                const double up = 1.0 + B, dn = 1.0 - B;
+                const double a1 = c == 0 ? up : dn, a2 = c == 0 ? dn : up;
+                const double x = dclip((a1 * xa_ + a2 * xb_) / 2.0, lb, ub);
+                const double mg = sh_mags[seg][c][k];
+                sh_vals[seg][c][k] =
+                    (float)dclip(x + pm_delta<NR>(x, lb, ub, mg, R.eta_m, nroot_m), lb, ub);
+            }
+        }
+
         // mutation sites (ascending) seen through a cursor per child: this
         // lane's quads ascend, so the next site at or after the quad is
         // found by advancing past the other lanes' sites
         const int32_t *st1 = sh_sites[seg][0], *st2 = sh_sites[seg][1];
-        const double *mg1 = sh_mags[seg][0], *mg2 = sh_mags[seg][1];
+        const float *mv1 = sh_vals[seg][0], *mv2 = sh_vals[seg][1];
         int p1 = 0, p2 = 0;
         int nx1 = n1 > 0 ? st1[0] : INT_MAX, nx2 = n2 > 0 ? st2[0] : INT_MAX;
 
@@ -542,37 +571,29 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                 c1v[k] = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
                 c2v[k] = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
             }
-            // polynomial mutation of the genes of this quad that are sites
-            while (nx1 < g0) nx1 = ++p1 < n1 ? st1[p1] : INT_MAX;
-            while (nx2 < g0) nx2 = ++p2 < n2 ? st2[p2] : INT_MAX;
-            // one pending site per lane and pass (usually a single pass), so
-            // the wave evaluates the mutation once rather than per gene
-            while (__any(nx1 < g0 + 4 || nx2 < g0 + 4)) {
-                const bool h1 = nx1 < g0 + 4;
-                if (h1 || nx2 < g0 + 4) {
-                    const int k = (h1 ? nx1 : nx2) - g0;
-                    double x = 0.0;
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-                        if (kk == k) x = h1 ? c1v[kk] : c2v[kk];
-                    const double mg = h1 ? mg1[p1] : mg2[p2];
-                    const double y = dclip(x + pm_delta<NR>(x, lb, ub, mg, R.eta_m, nroot_m), lb, ub);
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        if (h1 && kk == k) c1v[kk] = y;
-                        if (!h1 && kk == k) c2v[kk] = y;
-                    }
-                    if (h1)
-                        nx1 = ++p1 < n1 ? st1[p1] : INT_MAX;
-                    else
-                        nx2 = ++p2 < n2 ? st2[p2] : INT_MAX;
-                }
-            }
             float y1[4], y2[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 y1[k] = (float)c1v[k];
                 y2[k] = (float)c2v[k];
+            }
+            // genes of this quad that are mutation sites take their mutated
+            // values (the sites ascend, so each cursor moves forward only)
+            while (nx1 < g0) nx1 = ++p1 < n1 ? st1[p1] : INT_MAX;
+            while (nx2 < g0) nx2 = ++p2 < n2 ? st2[p2] : INT_MAX;
+            while (nx1 < g0 + 4) {
+                const float v = mv1[p1];
+                const int k = nx1 - g0;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) y1[kk] = kk == k ? v : y1[kk];
+                nx1 = ++p1 < n1 ? st1[p1] : INT_MAX;
+            }
+            while (nx2 < g0 + 4) {
+                const float v = mv2[p2];
+                const int k = nx2 - g0;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) y2[kk] = kk == k ? v : y2[kk];
+                nx2 = ++p2 < n2 ? st2[p2] : INT_MAX;
             }
             if (evaluate) {
                 // the quad's distance terms, summed in single precision and

@@ -290,10 +290,10 @@ __device__ __forceinline__ void child_ideal(const RunView &R, int64_t gen, bool 
     }
 }
 
+// x clipped to [lo, hi] (lo <= hi, x not NaN): one binary64 max and min
 __device__ __forceinline__ double dclip(double x, double lo, double hi)
 {
-    x = x < lo ? lo : x;
-    return x > hi ? hi : x;
+    return __builtin_fmin(__builtin_fmax(x, lo), hi);
 }
 
 }  // namespace rvea

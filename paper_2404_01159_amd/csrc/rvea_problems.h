@@ -12,30 +12,18 @@
 
 namespace rvea {
 
-// sin^2(pi x): with r = x - rint(x) in [-1/2, 1/2], sin^2(pi x) = sin^2(pi r)
-// (even, period 1), and sin(pi r) is its Taylor series through r^11
-// (truncation below 6e-8 at |r| = 1/2; single-precision result within
-// 3e-7 of sin^2 over the range used)
-__device__ __forceinline__ float sin2pi(float x)
-{
-    const float r = x - rintf(x);
-    const float u = r * r;
-    float p = -7.370430945714348e-3f;        // -pi^11/11!
-    p = fmaf(p, u, 8.214588661112819e-2f);     //  pi^9/9!
-    p = fmaf(p, u, -5.992645293207919e-1f);    // -pi^7/7!
-    p = fmaf(p, u, 2.550164039877345f);        //  pi^5/5!
-    p = fmaf(p, u, -5.167712780049969f);       // -pi^3/3!
-    p = fmaf(p, u, 3.141592653589793f);        //  pi
-    const float s = p * r;
-    return s * s;
-}
+// 2 sin^2(pi x) = 1 - cos(2 pi x), with the hardware cosine (its argument in
+// revolutions): measured absolute error below 1.3e-7 for |x| <= 2 against
+// binary64, and the term enters the objectives as (1 + g), so their relative
+// error from it stays below 2e-7
+__device__ __forceinline__ float two_sin2pi(float x) { return 1.0f - __builtin_amdgcn_cosf(x); }
 
 // distance term of one variable (before averaging)
 __device__ __forceinline__ float dist_term(int problem, float z)
 {
     const float t = z - 0.5f;
     if (problem == 2) return t * t;
-    return 10.0f * (t * t) + 2.0f * sin2pi(4.0f * t);
+    return 10.0f * (t * t) + two_sin2pi(4.0f * t);
 }
 
 // objectives from the m-1 position variables and the summed distance terms
