@@ -242,6 +242,7 @@ __device__ __forceinline__ double dotd(const double *a, const double *b)
 constexpr int kItems = 64;   // candidate tiles per row
 constexpr int kCache = 4;    // candidate chunks per lane kept in registers
 constexpr int kBatchRows = 8;  // rows per wave of the batched launch
+constexpr int kCand = 128;     // candidate vectors per wave after the binary32 prefilter
 
 // kRows rows per wave (4, 8 or 16): fewer rows give more waves to hide the
 // phases' memory latency on small populations, more rows less per-row
@@ -261,6 +262,14 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     __shared__ double s_gam[kWaveItems];  // gamma of the item's best vector (selection)
     __shared__ int s_bj[kWaveItems];
     __shared__ unsigned char s_dup[kWaveItems];
+    // selection rows: the row's binary32 f' and threshold, and the candidate
+    // vectors that pass the binary32 prefilter (row << 27 | vector), their
+    // count per row and their binary64 cosines
+    __shared__ float s_f32[kRows][MD];
+    __shared__ float s_thr[kRows];
+    __shared__ int s_rc[kRows];
+    __shared__ int s_cand[kCand];
+    __shared__ double s_cos[kCand];
 
     const int t = threadIdx.x;
     const int r = t / kLanes, sub = t % kLanes;
@@ -304,6 +313,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     }
     if (act) {
         double f[MD], nrm;
+        float f32[MD];
         float n2f = 0.f;
 #pragma unroll
         for (int k = 0; k < MD; ++k) {
@@ -317,6 +327,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
                 f[k] = (double)Fk - (double)zk;
                 fk = Fk - zk;
             }
+            f32[k] = fk;
             n2f = fmaf(fk, fk, n2f);
         }
         if (GAMMA) {
@@ -329,7 +340,10 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
         }
         if (sub == 0) {
 #pragma unroll
-            for (int k = 0; k < MD; ++k) s_f[r][k] = f[k];
+            for (int k = 0; k < MD; ++k) {
+                s_f[r][k] = f[k];
+                if (!GAMMA) s_f32[r][k] = f32[k];
+            }
             s_nrm[r] = nrm;
         }
         state = (!GAMMA && nrm == 0.0) ? 2 : 1;
@@ -369,6 +383,10 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     if (sub == 0) {
         s_state[r] = act ? state : 0;
         s_cnt[r] = (act && state == 1) ? tot : 0;
+        if (!GAMMA) {
+            s_thr[r] = thr;
+            s_rc[r] = 0;
+        }
     }
     __syncthreads();
     if (t == 0) {  // rows' item offsets, in row order; a row beyond the wave's capacity scans in full
@@ -403,9 +421,98 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     }
     __syncthreads();
 
-    // ---- phase 2: flattened (item, vector) space, 32 lanes per item
+    __shared__ double s_rb[kRows], s_rg[kRows];
+    __shared__ int s_rj[kRows], s_full[kRows];
     const int rounds = (total * kTile + 63) / 64;
-    for (int k = 0; k < rounds; ++k) {
+
+    // ---- phase 2, selection rows: the candidate tiles' vectors are scored
+    // in binary32 exactly as the association scored them (same f', same
+    // binary32 vectors, same operations), and only those at or above the
+    // row's threshold are kept: the binary64 maximum is among them (its
+    // binary32 score is within 2 eps of the binary32 maximum, like the tiles
+    // it lies in), and so is every vector tied with it.  Candidates are
+    // appended in row order, so each row's are contiguous.  More than kCand
+    // in the wave (vectors crowded below binary32 resolution): the tiles are
+    // taken whole instead, as for the gamma pass.
+    bool tiles = GAMMA;
+    if (!GAMMA) {
+        constexpr int NV4 = MD <= 4 ? 1 : 2;
+        const float4 *V4 = reinterpret_cast<const float4 *>(R.V32);
+        int ncand = 0;  // uniform
+        for (int k = 0; k < rounds; ++k) {
+            const int e = t + 64 * k;
+            const int item = e >> 5;
+            bool keep = false;
+            int code = 0, row = 0;
+            if (item < total) {
+                row = s_item[item] >> 27;
+                const int64_t j = (int64_t)(s_item[item] & ((1 << 27) - 1)) + (e & 31);
+                if (j < R.K) {
+                    float4 v[NV4];
+#pragma unroll
+                    for (int q = 0; q < NV4; ++q) v[q] = V4[j * NV4 + q];
+                    float fr[MD];
+#pragma unroll
+                    for (int kk = 0; kk < MD; ++kk) fr[kk] = s_f32[row][kk];
+                    keep = dotf<MD>(fr, v) >= s_thr[row];
+                    code = (row << 27) | (int)j;
+                }
+            }
+            const unsigned long long b = __ballot(keep);
+            const int pos = ncand + (int)__builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+            if (keep) {
+                if (pos < kCand) s_cand[pos] = code;
+                atomicAdd(&s_rc[row], 1);
+            }
+            ncand += __popcll(b);
+        }
+        tiles = ncand > kCand;
+        __syncthreads();
+        if (!tiles) {
+            // binary64 cosines of the candidates, one lane each
+            for (int q = t; q < ncand; q += 64) {
+                const int code = s_cand[q];
+                const int row = code >> 27;
+                const int64_t j = code & ((1 << 27) - 1);
+                double f[MD];
+#pragma unroll
+                for (int kk = 0; kk < MD; ++kk) f[kk] = s_f[row][kk];
+                s_cos[q] = dotd<MD>(f, R.V + j * MD) / (s_nrm[row] * R.vn[j]);
+            }
+            __syncthreads();
+            // ---- phase 3, selection rows: one lane per row, the best of its
+            // candidates (largest cosine, lowest index on ties)
+            if (t < kRows) {
+                const int st = s_state[t];
+                double best = -INFINITY;
+                int64_t bj = R.K;
+                bool full = st == 3;
+                if (st == 1) {
+                    int o = 0;
+                    for (int q = 0; q < t; ++q) o += s_rc[q];
+                    for (int q = o; q < o + s_rc[t]; ++q) {
+                        const double b2 = s_cos[q];
+                        const int64_t j = s_cand[q] & ((1 << 27) - 1);
+                        if (b2 > best || (b2 == best && j < bj)) {
+                            best = b2;
+                            bj = j;
+                        }
+                    }
+                    if (bj >= R.K) full = true;
+                }
+                s_full[t] = full ? 1 : 0;
+                s_rb[t] = best;
+                s_rg[t] = bj < R.K ? R.gamma[bj] : 0.0;
+                s_rj[t] = (int)bj;
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- phase 2 (gamma rows, or crowded selection rows): flattened
+    // (item, vector) space, 32 lanes per item, binary64 throughout
+    for (int k = 0; tiles && k < rounds; ++k) {
         const int e = t + 64 * k;
         const int item = e >> 5;
         double best = -INFINITY, gam = 0.0;
@@ -445,9 +552,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     __syncthreads();
 
     // ---- phase 3: one lane per row merges its items
-    __shared__ double s_rb[kRows], s_rg[kRows];
-    __shared__ int s_rj[kRows], s_full[kRows];
-    if (t < kRows) {
+    if (tiles && t < kRows) {
         const int st = s_state[t];
         double best = -INFINITY, gam = 0.0;
         int64_t bj = R.K;
