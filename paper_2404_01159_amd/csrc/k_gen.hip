@@ -697,10 +697,9 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
     }
 }
 
-// Workgroups of one wavefront: the pairs spread over the CUs in the finest
-// steps (the kernel's few wavefronts per SIMD make whole-workgroup
-// granularity visible as idle SIMDs).
-constexpr int kOffBlock = 64;
+// Workgroups of one wavefront (kOffBlock): the pairs spread over the CUs in
+// the finest steps (the kernel's few wavefronts per SIMD make
+// whole-workgroup granularity visible as idle SIMDs).
 
 template <int S, int NR, int DK>
 __global__ __launch_bounds__(kOffBlock) void k_offspring(RunView R)
@@ -752,11 +751,15 @@ __global__ __launch_bounds__(256) void kb_prep(const RunView *runs, const Span *
     const int s = find_span(sp, n, blockIdx.x);
     prep_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
-template <int S>
-__global__ __launch_bounds__(kBlock) void kb_offspring(const RunView *runs, const Span *sp, int n)
+// batched: one-wavefront workgroups as above; NR = 21 when every run of the
+// launch has the default distribution indices (the same arithmetic as the
+// general variant, so results do not depend on the batch's make-up)
+template <int S, int NR>
+__global__ __launch_bounds__(kOffBlock) void kb_offspring(const RunView *runs, const Span *sp,
+                                                          int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
-    offspring_body<S, 0, -1, kBlock>(runs[sp[s].run], blockIdx.x - sp[s].start);
+    offspring_body<S, NR, -1, kOffBlock>(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
 __global__ __launch_bounds__(256) void kb_offspring_finish(const RunView *runs, const Span *sp,
                                                            int n)
@@ -833,13 +836,19 @@ hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span 
     switch (phase) {
     case BP_PREP: kb_prep<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_OFFSPRING:
-        switch (cls) {
-        case 4: kb_offspring<4><<<g, kBlock, 0, s>>>(runs, sp, n); break;
-        case 8: kb_offspring<8><<<g, kBlock, 0, s>>>(runs, sp, n); break;
-        case 16: kb_offspring<16><<<g, kBlock, 0, s>>>(runs, sp, n); break;
-        case 32: kb_offspring<32><<<g, kBlock, 0, s>>>(runs, sp, n); break;
-        default: kb_offspring<64><<<g, kBlock, 0, s>>>(runs, sp, n); break;
-        }
+#define RVEA_KBOFF(NRV)                                                                      \
+    switch (cls & kSegMask) {                                                                \
+    case 4: kb_offspring<4, NRV><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;                \
+    case 8: kb_offspring<8, NRV><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;                \
+    case 16: kb_offspring<16, NRV><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;              \
+    case 32: kb_offspring<32, NRV><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;              \
+    default: kb_offspring<64, NRV><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;              \
+    }
+        if (cls & kDefaultIndices)
+            RVEA_KBOFF(21)
+        else
+            RVEA_KBOFF(0)
+#undef RVEA_KBOFF
         break;
     case BP_OFFSPRING_FIN: kb_offspring_finish<<<g, 256, 0, s>>>(runs, sp, n); break;
     default: return hipErrorInvalidValue;

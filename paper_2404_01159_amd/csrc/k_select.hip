@@ -242,7 +242,7 @@ __device__ __forceinline__ double dotd(const double *a, const double *b)
 constexpr int kItems = 64;   // candidate tiles per row
 constexpr int kCache = 4;    // candidate chunks per lane kept in registers
 constexpr int kBatchRows = 8;  // rows per wave of the batched launch
-constexpr int kCand = 128;     // candidate vectors per wave after the binary32 prefilter
+constexpr int kCand = 64;      // candidate vectors per wave after the binary32 prefilter
 
 // kRows rows per wave (4, 8 or 16): fewer rows give more waves to hide the
 // phases' memory latency on small populations, more rows less per-row
@@ -432,10 +432,11 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
     // binary32 score is within 2 eps of the binary32 maximum, like the tiles
     // it lies in), and so is every vector tied with it.  Candidates are
     // appended in row order, so each row's are contiguous.  More than kCand
-    // in the wave (vectors crowded below binary32 resolution): the tiles are
-    // taken whole instead, as for the gamma pass.
-    bool tiles = GAMMA;
-    if (!GAMMA) {
+    // in the wave (vectors crowded below binary32 resolution), or more than
+    // three candidate tiles per row on average (crowding again, decided before
+    // any scoring): the tiles are taken whole instead, as for the gamma pass.
+    bool tiles = GAMMA || total > 3 * kRows;
+    if (!tiles) {
         constexpr int NV4 = MD <= 4 ? 1 : 2;
         const float4 *V4 = reinterpret_cast<const float4 *>(R.V32);
         int ncand = 0;  // uniform
@@ -467,7 +468,7 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
             }
             ncand += __popcll(b);
         }
-        tiles = ncand > kCand;
+        tiles = ncand > kCand;  // uniform
         __syncthreads();
         if (!tiles) {
             // binary64 cosines of the candidates, one lane each

@@ -147,7 +147,9 @@ hipError_t launch_batch_vectors(int phase, int cls, const RunView *runs, const S
 // block counts and template classes of the batched phases
 int batch_phase_class(int phase, const RunView &R)
 {
-    if (phase == BP_OFFSPRING) return offspring_segment(R.d, R.N);
+    if (phase == BP_OFFSPRING)
+        return offspring_segment(R.d, R.N) |
+               (R.eta_c == 20.0 && R.eta_m == 20.0 ? kDefaultIndices : 0);
     if (phase == BP_ASSOC || phase == BP_RERANK || phase == BP_GAMMA_ASSOC ||
         phase == BP_GAMMA_RERANK)
         return R.m;
@@ -166,7 +168,7 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
     case BP_PREP: return (R.K + R.N + 255) / 256;
     case BP_OFFSPRING: {
         const int S = offspring_segment(R.d, R.N);
-        return ((R.N + 1) / 2 * R.osplit + (kBlock / S) - 1) / (kBlock / S);
+        return ((R.N + 1) / 2 * R.osplit + (kOffBlock / S) - 1) / (kOffBlock / S);
     }
     case BP_OFFSPRING_FIN:  // only runs whose pairs are split over segments
         return R.osplit > 1 ? (R.N + 255) / 256 : 0;

@@ -14,6 +14,11 @@ namespace rvea {
 void note_thread_error(const char *what, hipError_t e);
 void note_thread_message(const char *msg);
 
+constexpr int kOffBlock = 64;  // threads per workgroup of the offspring kernels
+// template class of a batched offspring launch: the segment width, plus
+// kDefaultIndices when the run has the default distribution indices
+constexpr int kSegMask = 0xff, kDefaultIndices = 0x100;
+
 int pick_segment(int d);                 // lanes per individual (initialization)
 int offspring_segment(int d, int64_t N);  // lanes per parent pair
 int offspring_splits(int d, int64_t N);   // segments per parent pair

@@ -167,3 +167,31 @@ def test_batch_rejects_single_run_calls(P):
         b.admit(r3)  # full
     b.step()
     assert r.get_state()["t"] == 1
+
+
+def test_batch_with_general_distribution_indices(P, O):
+    """A run with other distribution indices and crossover rate (the general
+    offspring variant) batched beside default runs: every generation of each
+    against the oracle, and equal to the same runs alone."""
+    prm_g = P.default_params(t_max=30, eta_c=15.0, eta_m=5.0, p_c=0.7, p_m=2.0)
+    prm_d = P.default_params(t_max=30)
+    specs = [(1, 3, 300, 105, 105, 21, prm_g), (2, 3, 64, 91, 91, 22, prm_d),
+             (3, 2, 2048, 64, 64, 23, prm_g)]
+    mixed = [P.Run(pb, m, d, N, K, seed=sd, params=pr) for pb, m, d, N, K, sd, pr in specs]
+    alone = [P.Run(pb, m, d, N, K, seed=sd, params=pr) for pb, m, d, N, K, sd, pr in specs]
+    batch = P.Batch(4)
+    for r in mixed:
+        batch.admit(r)
+    stats = new_stats()
+    for _ in range(7):
+        before = [r.get_state() for r in mixed]
+        batch.step()
+        for r, st, sp in zip(mixed, before, specs):
+            check_generation(O, r, sp[6], st, r.get_offspring(), r.get_selection(), r.get_state(),
+                             stats)
+    for r in alone:
+        r.run(7)
+    for a, b in zip(alone, mixed):
+        assert same(a, b) is None, same(a, b)
+    assert stats["straddles"] <= max(2, 1e-6 * stats["genes"]), stats
+    assert stats["near_ties"] <= max(1, 1e-4 * stats["vectors"]), stats
