@@ -285,6 +285,7 @@ __device__ __forceinline__ double seg_sum(double v)
     if constexpr (S >= 16) v += partner32<3>(v);
     if constexpr (S >= 32) v += partner32<4>(v);
     if constexpr (S == 64) {
+        RVEA_ASSERT_FULL_WAVE();
         const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
                                           __builtin_amdgcn_readlane(__double2loint(v), 0));
         const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),

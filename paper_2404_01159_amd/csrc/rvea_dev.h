@@ -210,12 +210,30 @@ __device__ __forceinline__ int64_t partner32(int64_t x)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// The whole-wavefront helpers below (wave_incl_scan, wave_min, wave_max,
+// and seg_sum<64> in k_gen.hip) read neighbouring lanes through DPP and lane
+// reads, so they are correct only with all 64 lanes active; every call site
+// is outside divergent code.  A build with -DRVEA_CHECK_LANES stops a
+// wavefront that calls one with inactive lanes (a debugging aid, never
+// enabled in the library or its tests).
+#ifdef RVEA_CHECK_LANES
+#define RVEA_ASSERT_FULL_WAVE()                                                              \
+    do {                                                                                     \
+        if (__builtin_amdgcn_read_exec() != ~0ull) __builtin_trap();                         \
+    } while (0)
+#else
+#define RVEA_ASSERT_FULL_WAVE() \
+    do {                        \
+    } while (0)
+#endif
+
 // Inclusive prefix sum over the 64 lanes of a converged wavefront (DPP):
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes (lanes without a
 // source add 0), then each row adds the last lane of the rows before it
 // (row broadcasts of lanes 15 and 31).
 __device__ __forceinline__ int wave_incl_scan(int v)
 {
+    RVEA_ASSERT_FULL_WAVE();
     v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
     v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
     v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
@@ -236,6 +254,7 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
 }
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 {
+    RVEA_ASSERT_FULL_WAVE();
     v = min(v, dpp_u32<0xB1>(v));   // quad_perm [1,0,3,2]
     v = min(v, dpp_u32<0x4E>(v));   // quad_perm [2,3,0,1]
     v = min(v, dpp_u32<0x141>(v));  // row_half_mirror
@@ -248,6 +267,7 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 }
 __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
+    RVEA_ASSERT_FULL_WAVE();
     v = max(v, dpp_u32<0xB1>(v));
     v = max(v, dpp_u32<0x4E>(v));
     v = max(v, dpp_u32<0x141>(v));

@@ -33,7 +33,7 @@ namespace {
 constexpr int kMaxObj = 8;
 constexpr int64_t kMaxRows = (int64_t)1 << 24;   // rows and weights of the expected utility
 constexpr int64_t kMaxHvRows = (int64_t)1 << 18;  // rows of the hypervolume (O(n^2) work)
-constexpr int kRankChunk = 4096;  // k-range counted by one workgroup of k_hv_rank
+constexpr int kRankChunk = 512;  // k-range counted by one workgroup of k_hv_rank
 
 struct Norm {
     double lo[kMaxObj], inv[kMaxObj];  // f' = (f - lo) / (hi - lo), scale given as hi - lo
