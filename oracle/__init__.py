@@ -32,6 +32,18 @@ class OraParams(C.Structure):
     ]
 
 
+class OraOp(C.Structure):
+    _fields_ = [("op", C.c_int32), ("pad_", C.c_int32), ("a", C.c_double), ("b", C.c_double)]
+
+
+OP_GA, OP_DE, OP_PSO, OP_CSO, OP_RAND = 0, 1, 2, 3, 4
+
+
+def op_params(op, a=0.0, b=0.0):
+    """ora_op: DE (a = F, b = CR), PSO (a = w, b = c), CSO and random (unused)."""
+    return OraOp(int(op), 0, float(a), float(b))
+
+
 class OraLQ(C.Structure):
     _fields_ = [
         ("A", C.c_void_p),
@@ -106,6 +118,10 @@ def lib():
             "ora_generation": (i32, [P, i32, i32, i32, i64, i64, u64, i64, P, P, P, P, P, P,
                                      P, P, P, P, P]),
             "ora_run": (i32, [P, i32, i32, i32, i64, i64, u64, i32, P, P, P, P, P, P]),
+            "ora_de_draws": (i32, [u64, i64, i64, i32, P, i64, P]),
+            "ora_reproduce_op": (i32, [P, P, u64, i64, i64, i64, i32, i32, P, P, P, P, P, P]),
+            "ora_generation_op": (i32, [P, P, i32, i32, i32, i64, i64, u64, i64, P, P, P, P, P,
+                                        P, P, P, P, P, P, P]),
             "ora_hypervolume": (f64, [i32, i64, P, P, P, P]),
             "ora_expected_utility": (f64, [i32, i64, P, P, P, P, i64, P]),
             "ora_num_threads": (i32, []),
@@ -429,6 +445,50 @@ def run(prm, problem, m, d, N, K, seed, gens):
     if rc != 0:
         raise RuntimeError(f"ora_run failed ({rc})")
     return State(X, F, valid, V, V0, g)
+
+
+def de_draws(seed, t, o, d, valid):
+    """DE/rand/1/bin draws of child o: (target, r1, r2, r3, j_rand)."""
+    P = _c(np.nonzero(_c(valid, np.uint8))[0], np.int32)
+    out = np.zeros(5, np.int32)
+    if lib().ora_de_draws(seed, t, o, d, _p(P), len(P), _p(out)) != 0:
+        raise ValueError("no valid slot")
+    return tuple(int(x) for x in out)
+
+
+def reproduce_op(prm, op, seed, t, X, Vel, valid, F, N):
+    """Offspring (N x d) and their velocities by operator ``op`` (op_params)
+    from the slot-ordered population X (K x d), velocities Vel (K x d or
+    None), valid flags and objectives F (K x m)."""
+    X = _c(X, np.float32)
+    K, d = X.shape
+    F = _c(F, np.float64)
+    m = F.shape[1]
+    Vel = _c(np.zeros((K, d), np.float32) if Vel is None else Vel, np.float32)
+    Xoff = np.zeros((N, d), np.float32)
+    Voff = np.zeros((N, d), np.float32)
+    rc = lib().ora_reproduce_op(C.byref(prm), C.byref(op), seed, t, K, N, d, m, _p(X), _p(Vel),
+                                _p(_c(valid, np.uint8)), _p(F), _p(Xoff), _p(Voff))
+    if rc != 0:
+        raise ValueError(f"ora_reproduce_op failed ({rc})")
+    return Xoff, Voff
+
+
+def generation_op(prm, op, problem, m, d, N, K, seed, t, st, Vel):
+    """Advance ``st`` (and the K x d slot velocities ``Vel``) in place by
+    generation t with operator ``op``; returns the stage outputs."""
+    Xoff = np.zeros((N, d), np.float32)
+    Voff = np.zeros((N, d), np.float32)
+    Foff = np.zeros((N, m), np.float64)
+    surv = np.zeros(K, np.int32)
+    adapted = C.c_int(0)
+    rc = lib().ora_generation_op(C.byref(prm), C.byref(op), problem, m, d, N, K, seed, t,
+                                 _p(st.X), _p(Vel), _p(st.F), _p(st.valid), _p(st.V), _p(st.V0),
+                                 _p(st.gamma), _p(Xoff), _p(Voff), _p(Foff), _p(surv),
+                                 C.byref(adapted))
+    if rc != 0:
+        raise RuntimeError(f"ora_generation_op failed ({rc})")
+    return dict(Xoff=Xoff, Voff=Voff, Foff=Foff, surv=surv, adapted=bool(adapted.value))
 
 
 def hypervolume(F, valid=None, lo=None, hi=None):

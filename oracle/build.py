@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rvea_oracle.c")
-SRCS = [SRC, os.path.join(HERE, "indicators.c")]
+SRCS = [SRC, os.path.join(HERE, "indicators.c"), os.path.join(HERE, "operators.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -22,6 +22,20 @@ extern "C" {
 #define ORA_TAG_SBX 2u
 #define ORA_TAG_SBXPAIR 3u
 #define ORA_TAG_MUT 4u
+#define ORA_TAG_OPSEL 5u  /* other operators: selection draws */
+#define ORA_TAG_OPGENE 6u /* other operators: per-gene uniforms */
+
+/* reproduction operators of the extensibility experiments (operators.c) */
+#define ORA_OP_GA 0 /* SBX + polynomial mutation (Appendix B), rvea_oracle.c */
+#define ORA_OP_DE 1
+#define ORA_OP_PSO 2
+#define ORA_OP_CSO 3
+#define ORA_OP_RAND 4
+typedef struct ora_op {
+    int32_t op;
+    int32_t pad_;
+    double a, b; /* DE: F, CR; PSO: w, c; CSO, random: unused */
+} ora_op;
 
 /* Linear system of the policy-rollout problem (problem id ORA_POLICY_LQ):
  * A 32x32 and B 32x8 row-major, x0 E x 32 rollout start states, T steps,
@@ -96,6 +110,17 @@ int ora_generation(const ora_params *P, int problem, int m, int d, int64_t N, in
                    int32_t *parents_out, int32_t *surv_out, int *adapted);
 int ora_run(const ora_params *P, int problem, int m, int d, int64_t N, int64_t K, uint64_t seed,
             int gens, float *X, double *F, uint8_t *valid, double *V, double *V0, double *gamma);
+/* operators.c: DE, PSO, CSO and random reproduction */
+int ora_de_draws(uint64_t seed, int64_t t, int64_t o, int d, const int32_t *P, int64_t nv,
+                 int32_t out[5]);
+int ora_reproduce_op(const ora_params *Pr, const ora_op *op, uint64_t seed, int64_t t,
+                     int64_t K, int64_t N, int d, int m, const float *X, const float *Vel,
+                     const uint8_t *valid, const double *F, float *Xoff, float *Voff);
+int ora_generation_op(const ora_params *Pr, const ora_op *op, int problem, int m, int d,
+                      int64_t N, int64_t K, uint64_t seed, int64_t t, float *X, float *Vel,
+                      double *F, uint8_t *valid, double *V, const double *V0, double *gamma,
+                      float *Xoff_out, float *Voff_out, double *Foff_out, int32_t *surv_out,
+                      int *adapted);
 /* indicators.c: App. C.2 hypervolume (m = 2, 3; reference point ones on
  * f' = (f - lo) / (hi - lo)) and the expected utility over a weight set */
 double ora_hypervolume(int m, int64_t n, const double *F, const uint8_t *valid, const double *lo,
