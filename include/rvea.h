@@ -67,23 +67,62 @@ typedef enum rvea_problem {
     RVEA_POLICY_LQ = 100 /* policy rollouts, m = 2, d = 6728; see rvea_create_policy */
 } rvea_problem;
 
+/* Reproduction operators (Sec. 4, Extensibility: the genetic operators
+ * swapped for those of other population methods, selection and adaptation
+ * unchanged).  The paper names the operators without defining them; each
+ * is the update of its original method:
+ *   RVEA_OP_GA   SBX + polynomial mutation on random pairs (Appendix B);
+ *   RVEA_OP_DE   DE/rand/1/bin (Storn and Price): per child a target and
+ *                three distinct donors from the population, mutant
+ *                x_r1 + F (x_r2 - x_r3) clipped to the box, binomial
+ *                crossover with rate CR and one forced gene;
+ *                op_a = F in [0, 2], op_b = CR in [0, 1];
+ *   RVEA_OP_PSO  particle swarm with inertia weight (Kennedy and Eberhart;
+ *                Shi and Eberhart): per child a particle i and a leader l
+ *                drawn from the population, v' = w v_i + c r (x_l - x_i)
+ *                with r uniform per gene, x' = clip(x_i + v'); every
+ *                individual carries its velocity (zero when created);
+ *                op_a = w in [0, 1], op_b = c in [0, 4];
+ *   RVEA_OP_CSO  competitive swarm (Cheng and Jin): per pair of drawn
+ *                members the one with the smaller objective sum wins; the
+ *                loser moves, v' = r1 v_l + r2 (x_w - x_l), and the winner
+ *                is carried over unchanged; op_a = op_b = 0;
+ *   RVEA_OP_RAND every child drawn uniformly in the box (the study's
+ *                baseline); op_a = op_b = 0.
+ * Random draws come from the run's Philox4x32-10 streams; the exact
+ * counters are stated in the library's oracle.  Operators other than GA
+ * run as single runs only (rvea_batch_admit returns RVEA_EUNSUPPORTED). */
+typedef enum rvea_operator {
+    RVEA_OP_GA = 0,
+    RVEA_OP_DE = 1,
+    RVEA_OP_PSO = 2,
+    RVEA_OP_CSO = 3,
+    RVEA_OP_RAND = 4
+} rvea_operator;
+
 /* Algorithm parameters (defaults from rvea_default_params in brackets). */
 typedef struct rvea_params {
     double alpha;     /* APD penalty rate of Eq. 4 [2] */
     double fr;        /* adaptation every ceil(fr * t_max) generations [0.1] */
     int32_t t_max;    /* maximal number of generations, Eq. 4 [100] */
-    int32_t reserved; /* must be 0 */
+    int32_t op;       /* reproduction operator, rvea_operator [RVEA_OP_GA] */
     double eta_c;     /* SBX distribution index eta, Appendix B [20] */
     double eta_m;     /* polynomial-mutation distribution index xi [20] */
     double p_c;       /* crossover probability [1] */
     double p_m;       /* mutation probability; per-gene rate p_m/d, 0..4 [1] */
     double lb, ub;    /* box of every decision variable, lb < ub [0, 1] */
+    double op_a, op_b; /* the operator's parameters (see rvea_operator) [0, 0] */
 } rvea_params;
 
 typedef struct rvea_run_s *rvea_run;
 
 /* Fills *out with the defaults above. */
 rvea_status rvea_default_params(rvea_params *out);
+
+/* Selects operator op in *params and sets op_a, op_b to its defaults
+ * (DE: F = 0.5, CR = 0.9; PSO: w = 0.5, c = 1.5; others 0); the other
+ * fields are left as they are.  RVEA_EINVAL for an unknown operator. */
+rvea_status rvea_operator_params(int op, rvea_params *params);
 
 /* Reference-vector lattice (Alg. 2 input V_0): K = C(H+m-1, m-1) unit
  * vectors of the Das-Dennis simplex lattice with H divisions.  Writes the
@@ -188,7 +227,8 @@ rvea_status rvea_set_state(rvea_run run, const float *X, const float *F,
                            int64_t t);
 
 /* The offspring X (N x d float), their objectives F (N x m float) and the
- * mating pairs (ceil(N/2) x 2 slot indices) of the generation in progress
+ * mating pairs (ceil(N/2) x 2 slot indices; for RVEA_OP_CSO the pair's
+ * winner and loser, for the other non-GA operators -1) of the generation in progress
  * (after rvea_step) or, between generations, of the last completed one
  * (also after rvea_run_generations or a batch step; the next rvea_step
  * reuses their rows).  RVEA_ESTATE when no generation has completed since
@@ -202,6 +242,19 @@ rvea_status rvea_get_offspring(rvea_run run, float *X, float *F, int32_t *parent
  * (K int32 merged-row index, -1 if none).  Waits for the stream. */
 rvea_status rvea_get_selection(rvea_run run, float *zstar, int32_t *assoc, double *apd,
                                int32_t *surv);
+
+/* Velocities of the swarm operators (RVEA_OP_PSO, RVEA_OP_CSO): those of
+ * the population's slots (offspring = 0; K x d float, 0 for empty slots;
+ * valid between generations) or of the offspring (offspring = 1; N x d
+ * float; valid whenever rvea_get_offspring is).  A velocity belongs to its
+ * individual: a survivor keeps the one it was created with.  RVEA_EINVAL
+ * for runs of other operators.  Waits for the stream. */
+rvea_status rvea_get_velocities(rvea_run run, int offspring, float *Vel);
+
+/* Sets the slots' velocities (K x d float, rows of empty slots ignored)
+ * of a PSO or CSO run; rvea_set_state sets them to zero.  Only allowed
+ * between generations. */
+rvea_status rvea_set_velocities(rvea_run run, const float *Vel);
 
 /* Selected rows only: idx[0..n) are slot indices (offspring = 0) or
  * offspring indices (offspring = 1); writes their genes (n x d float) and

@@ -270,31 +270,6 @@ __device__ __forceinline__ double sbx_beta(double mc, double eta, int nrt)
     return sbx_beta_pow(mc, eta);
 }
 
-// Sum over the S lanes of a segment (S a power of two, 4 <= S <= 64; a
-// segment's lanes are all active or all inactive): the pairings of
-// partner32, which stay within groups of S lanes, then for a whole
-// wavefront the two halves' sums read out and added.  Every lane of the
-// segment ends with the same value.
-template <int S>
-__device__ __forceinline__ double seg_sum(double v)
-{
-    static_assert(S >= 4 && S <= 64 && (S & (S - 1)) == 0, "segment width");
-    v += partner32<0>(v);
-    v += partner32<1>(v);
-    if constexpr (S >= 8) v += partner32<2>(v);
-    if constexpr (S >= 16) v += partner32<3>(v);
-    if constexpr (S >= 32) v += partner32<4>(v);
-    if constexpr (S == 64) {
-        RVEA_ASSERT_FULL_WAVE();
-        const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
-                                          __builtin_amdgcn_readlane(__double2loint(v), 0));
-        const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
-                                          __builtin_amdgcn_readlane(__double2loint(v), 32));
-        v = a + b;
-    }
-    return v;
-}
-
 // ------------------------------------------------------------------- init
 // Slot i < N: genes from counter (q, i, 0, TAG_INIT), gene 4q+k from word k,
 // x = lb + (ub-lb) u24 rounded to float; evaluated in the same pass.
@@ -906,6 +881,7 @@ void launch_offspring_as(const RunView &R, hipStream_t s)
 
 hipError_t launch_offspring(const RunView &R, hipStream_t s)
 {
+    if (R.op != OP_GA) return launch_operator(R, s);
     // the default distribution indices (eta_c = eta_m = 20) get the root
     // index compiled in; any other run takes the general kernel
     if (R.eta_c == 20.0 && R.eta_m == 20.0) {

@@ -14,7 +14,14 @@ namespace rvea {
 
 // Philox stream tags (fourth counter word).  The other three counter words
 // are (sub-index, individual or pair, generation); the key is the run seed.
-enum : uint32_t { TAG_INIT = 0, TAG_MATE = 1, TAG_SBX = 2, TAG_SBXPAIR = 3, TAG_MUT = 4 };
+enum : uint32_t {
+    TAG_INIT = 0, TAG_MATE = 1, TAG_SBX = 2, TAG_SBXPAIR = 3, TAG_MUT = 4,
+    TAG_OPSEL = 5,  // member draws of the other reproduction operators
+    TAG_OPGENE = 6  // their per-gene uniforms
+};
+
+// reproduction operators (ids as in rvea.h)
+enum : int { OP_GA = 0, OP_DE = 1, OP_PSO = 2, OP_CSO = 3, OP_RAND = 4 };
 
 constexpr int kMaxM = 8;         // objectives supported
 constexpr int kTile = 32;        // reference vectors per association tile
@@ -48,6 +55,9 @@ struct RunView {
     int32_t *parents;   // ceil(N/2) x 2 slot indices
     int osplit;         // segments per parent pair in the offspring kernel (1: one)
     double *gpart;      // ceil(N/2) x osplit x 2 partial distance sums (osplit > 1)
+    int op;             // reproduction operator (OP_*)
+    double op_a, op_b;  // its parameters
+    float *Vel;         // (K+N) x ld velocities by physical row (PSO, CSO), else null
     int32_t *vs;        // K x 2: valid slots, ascending, each with its physical row
     int32_t *nvalid;    // 1
     int32_t *stamp;     // K+N: the generation that will read the row (rows of
@@ -211,7 +221,7 @@ __device__ __forceinline__ int64_t partner32(int64_t x)
 }
 
 // The whole-wavefront helpers below (wave_incl_scan, wave_min, wave_max,
-// and seg_sum<64> in k_gen.hip) read neighbouring lanes through DPP and lane
+// seg_sum<64>) read neighbouring lanes through DPP and lane
 // reads, so they are correct only with all 64 lanes active; every call site
 // is outside divergent code.  A build with -DRVEA_CHECK_LANES stops a
 // wavefront that calls one with inactive lanes (a debugging aid, never
@@ -226,6 +236,31 @@ __device__ __forceinline__ int64_t partner32(int64_t x)
     do {                        \
     } while (0)
 #endif
+
+// Sum over the S lanes of a segment (S a power of two, 4 <= S <= 64; a
+// segment's lanes are all active or all inactive): the pairings of
+// partner32, which stay within groups of S lanes, then for a whole
+// wavefront the two halves' sums read out and added.  Every lane of the
+// segment ends with the same value.
+template <int S>
+__device__ __forceinline__ double seg_sum(double v)
+{
+    static_assert(S >= 4 && S <= 64 && (S & (S - 1)) == 0, "segment width");
+    v += partner32<0>(v);
+    v += partner32<1>(v);
+    if constexpr (S >= 8) v += partner32<2>(v);
+    if constexpr (S >= 16) v += partner32<3>(v);
+    if constexpr (S >= 32) v += partner32<4>(v);
+    if constexpr (S == 64) {
+        RVEA_ASSERT_FULL_WAVE();
+        const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                          __builtin_amdgcn_readlane(__double2loint(v), 0));
+        const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                          __builtin_amdgcn_readlane(__double2loint(v), 32));
+        v = a + b;
+    }
+    return v;
+}
 
 // Inclusive prefix sum over the 64 lanes of a converged wavefront (DPP):
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes (lanes without a

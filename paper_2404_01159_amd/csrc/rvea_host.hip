@@ -32,7 +32,7 @@ enum Buf {
     B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_MVALID, B_PARENTS, B_VS,
     B_NVALID, B_STAMP, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
     B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_BCOUNT, B_FREECNT, B_PEN,
-    B_NDONE, B_LQ, B_GPART, B_COUNT
+    B_NDONE, B_LQ, B_GPART, B_VEL, B_COUNT
 };
 
 int64_t binomial(int64_t n, int64_t k)
@@ -67,14 +67,30 @@ rvea_status check_args(int problem, int m, int d, int64_t N, int64_t K, const rv
     if (m < 2 || m > kMaxM || d < m || d > (1 << 26)) return RVEA_EINVAL;
     if (K < 1 || K > (int64_t)1 << 27 || N < 1 || N > K) return RVEA_EINVAL;
     if (find_H(m, K) == 0) return RVEA_EINVAL;
-    if (!(p.alpha >= 0) || !(p.fr > 0) || p.t_max < 1 || p.reserved != 0) return RVEA_EINVAL;
+    if (!(p.alpha >= 0) || !(p.fr > 0) || p.t_max < 1) return RVEA_EINVAL;
+    switch (p.op) {  // the operator's parameters (rvea.h); unused ones must be 0
+    case OP_DE:
+        if (!(p.op_a >= 0 && p.op_a <= 2) || !(p.op_b >= 0 && p.op_b <= 1)) return RVEA_EINVAL;
+        break;
+    case OP_PSO:
+        if (!(p.op_a >= 0 && p.op_a <= 1) || !(p.op_b >= 0 && p.op_b <= 4)) return RVEA_EINVAL;
+        break;
+    case OP_GA:
+    case OP_CSO:
+    case OP_RAND:
+        if (p.op_a != 0.0 || p.op_b != 0.0) return RVEA_EINVAL;
+        break;
+    default: return RVEA_EINVAL;
+    }
     if (!(p.eta_c >= 0) || !(p.eta_m >= 0) || !(p.p_c >= 0 && p.p_c <= 1)) return RVEA_EINVAL;
     if (!(p.p_m >= 0 && p.p_m <= 4)) return RVEA_EINVAL;
     if (!(p.lb < p.ub) || !std::isfinite(p.lb) || !std::isfinite(p.ub)) return RVEA_EINVAL;
     return RVEA_OK;
 }
 
-void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
+bool swarm(int op) { return op == OP_PSO || op == OP_CSO; }
+
+void make_layout(int problem, int m, int d, int64_t N, int64_t K, int op, Layout &L)
 {
     const int64_t M = K + N;
     L.ld = (d + 31) / 32 * 32;
@@ -90,7 +106,7 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
     L.CS = (int)cs;
     L.KC = (int)((K + cs - 1) / cs);
     const int64_t P = (N + 1) / 2;
-    L.osplit = offspring_splits(d, N);
+    L.osplit = op == OP_GA ? offspring_splits(d, N) : 1;
     const size_t sz[B_COUNT] = {
         (size_t)(K + N) * L.ld * 4, (size_t)2 * K * 4, (size_t)N * 4, (size_t)2 * K,
         (size_t)2 * M * m * 4, (size_t)M,
@@ -100,7 +116,8 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, Layout &L)
         (size_t)M * 4, (size_t)M * 8, (size_t)K * 8, (size_t)K * 4, 8, 3 * 8, 4,
         (size_t)((K + N + 255) / 256) * 4, 4, 8, 4,
         problem == kPolicy ? (size_t)kLqFloats * 4 : 0,
-        L.osplit > 1 ? (size_t)P * L.osplit * 2 * 8 : 8};
+        L.osplit > 1 ? (size_t)P * L.osplit * 2 * 8 : 8,
+        swarm(op) ? (size_t)(K + N) * L.ld * 4 : 8};
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -268,13 +285,28 @@ rvea_status rvea_default_params(rvea_params *out)
     out->alpha = 2.0;
     out->fr = 0.1;
     out->t_max = 100;
-    out->reserved = 0;
+    out->op = OP_GA;
     out->eta_c = 20.0;
     out->eta_m = 20.0;
     out->p_c = 1.0;
     out->p_m = 1.0;
     out->lb = 0.0;
     out->ub = 1.0;
+    out->op_a = 0.0;
+    out->op_b = 0.0;
+    return RVEA_OK;
+}
+
+rvea_status rvea_operator_params(int op, rvea_params *p)
+{
+    if (!p) return RVEA_EINVAL;
+    switch (op) {
+    case OP_GA: case OP_CSO: case OP_RAND: p->op_a = 0.0; p->op_b = 0.0; break;
+    case OP_DE: p->op_a = 0.5; p->op_b = 0.9; break;   // F, CR
+    case OP_PSO: p->op_a = 0.5; p->op_b = 1.5; break;  // w, c
+    default: return RVEA_EINVAL;
+    }
+    p->op = op;
     return RVEA_OK;
 }
 
@@ -296,7 +328,7 @@ rvea_status rvea_footprint(int problem, int m, int d, int64_t N, int64_t K,
     const rvea_status st = check_args(problem, m, d, N, K, p);
     if (st != RVEA_OK) return st;
     Layout L;
-    make_layout(problem, m, d, N, K, L);
+    make_layout(problem, m, d, N, K, p.op, L);
     *bytes = L.total;
     return RVEA_OK;
 }
@@ -327,7 +359,7 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
         }
     }
     Layout L;
-    make_layout(problem, m, d, N, K, L);
+    make_layout(problem, m, d, N, K, p.op, L);
     if (workspace_bytes < L.total) return RVEA_ENOMEM;
 
     rvea_run r = new rvea_run_s();
@@ -383,6 +415,10 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.parents = (int32_t *)(w + L.off[B_PARENTS]);
     R.osplit = L.osplit;
     R.gpart = (double *)(w + L.off[B_GPART]);
+    R.op = p.op;
+    R.op_a = p.op_a;
+    R.op_b = p.op_b;
+    R.Vel = swarm(p.op) ? (float *)(w + L.off[B_VEL]) : nullptr;
     R.vs = (int32_t *)(w + L.off[B_VS]);
     R.nvalid = (int32_t *)(w + L.off[B_NVALID]);
     R.stamp = (int32_t *)(w + L.off[B_STAMP]);
@@ -428,6 +464,8 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     if (e == hipSuccess)
         e = hipMemsetAsync(R.counters, 0, 3 * sizeof(unsigned long long), r->stream);
     if (e == hipSuccess) e = hipMemsetAsync(R.vchanged, 0, 4, r->stream);
+    if (e == hipSuccess && R.Vel)  // every individual starts at rest
+        e = hipMemsetAsync(R.Vel, 0, (size_t)(K + N) * L.ld * 4, r->stream);
     if (e == hipSuccess) e = hipMemsetAsync(R.ndone, 0, 4, r->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(R.stamp, 0xff, (size_t)(K + N) * 4, r->stream);
@@ -643,20 +681,23 @@ rvea_status rvea_synchronize(rvea_run r)
 
 namespace {
 
-// copy the gene rows rows[0..n) of the pool into dst (n x d, host)
-rvea_status copy_rows(rvea_run r, const std::vector<int32_t> &rows, float *dst)
+// copy the rows rows[0..n) of a (K+N) x ld pool (the genes by default, or
+// the velocities) into dst (n x d, host)
+rvea_status copy_rows(rvea_run r, const std::vector<int32_t> &rows, float *dst,
+                      const float *pool_base = nullptr)
 {
     const RunView &R = r->R;
+    const float *base = pool_base ? pool_base : R.X;
     const size_t rowb = (size_t)R.d * 4;
     const size_t pool_bytes = (size_t)(R.K + R.N) * R.ld * 4;
     if (pool_bytes <= ((size_t)1 << 28) || rows.size() * 4 > (size_t)(R.K + R.N)) {
         std::vector<float> pool((size_t)(R.K + R.N) * R.ld);
-        HIPCHK(r, hipMemcpy(pool.data(), R.X, pool_bytes, hipMemcpyDeviceToHost));
+        HIPCHK(r, hipMemcpy(pool.data(), base, pool_bytes, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < rows.size(); ++i)
             std::memcpy(dst + i * R.d, pool.data() + (size_t)rows[i] * R.ld, rowb);
     } else {
         for (size_t i = 0; i < rows.size(); ++i)
-            HIPCHK(r, hipMemcpy(dst + i * R.d, R.X + (size_t)rows[i] * R.ld, rowb,
+            HIPCHK(r, hipMemcpy(dst + i * R.d, base + (size_t)rows[i] * R.ld, rowb,
                                 hipMemcpyDeviceToHost));
     }
     return RVEA_OK;
@@ -748,6 +789,7 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
     HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemset(R.stamp, 0xff, (size_t)(R.K + R.N) * 4));
     HIPCHK(r, hipMemset(R.zbits, 0xff, (size_t)2 * R.m * 4));
+    if (R.Vel) HIPCHK(r, hipMemset(R.Vel, 0, (size_t)(R.K + R.N) * R.ld * 4));
     HIPCHK(r, hipDeviceSynchronize());
     HIPCHK(r, launch_stamp(R, r->stream));
     HIPCHK(r, hipStreamSynchronize(active_stream(r)));
@@ -832,6 +874,54 @@ rvea_status rvea_get_rows(rvea_run r, int offspring, const int64_t *idx, int64_t
                                 (size_t)R.m * 4, hipMemcpyDeviceToHost));
     }
     return check_counters(r);
+}
+
+rvea_status rvea_get_velocities(rvea_run r, int offspring, float *Vel)
+{
+    if (!r || !Vel) return RVEA_EINVAL;
+    const RunView &R = r->R;
+    if (!R.Vel) return RVEA_EINVAL;
+    if (offspring && !offspring_readable(r)) return RVEA_ESTATE;
+    if (!offspring && r->phase != 0) return RVEA_ESTATE;
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
+    int64_t td = 0;
+    rvea_status st = device_t(r, &td);
+    if (st != RVEA_OK) return st;
+    const int64_t n = offspring ? R.N : R.K;
+    std::vector<int32_t> rows(n);
+    HIPCHK(r, hipMemcpy(rows.data(), offspring ? R.off_row : slot_rows_at(R, td), n * 4,
+                        hipMemcpyDeviceToHost));
+    st = copy_rows(r, rows, Vel, R.Vel);
+    if (st != RVEA_OK) return st;
+    if (!offspring) {
+        std::vector<uint8_t> vh(R.K);
+        HIPCHK(r, hipMemcpy(vh.data(), valids_at(R, td), R.K, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < R.K; ++j)
+            if (!vh[j]) std::memset(Vel + j * R.d, 0, (size_t)R.d * 4);
+    }
+    return RVEA_OK;
+}
+
+rvea_status rvea_set_velocities(rvea_run r, const float *Vel)
+{
+    if (!r || !Vel) return RVEA_EINVAL;
+    const RunView &R = r->R;
+    if (!R.Vel) return RVEA_EINVAL;
+    if (r->phase != 0 || r->batch) return RVEA_ESTATE;
+    HIPCHK(r, hipStreamSynchronize(active_stream(r)));
+    int64_t td = 0;
+    rvea_status st = device_t(r, &td);
+    if (st != RVEA_OK) return st;
+    std::vector<int32_t> rows(R.K);
+    HIPCHK(r, hipMemcpy(rows.data(), slot_rows_at(R, td), R.K * 4, hipMemcpyDeviceToHost));
+    // the pool through host memory: the slots' rows are scattered over it
+    const size_t pool_bytes = (size_t)(R.K + R.N) * R.ld * 4;
+    std::vector<float> pool((size_t)(R.K + R.N) * R.ld);
+    HIPCHK(r, hipMemcpy(pool.data(), R.Vel, pool_bytes, hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < R.K; ++j)
+        std::memcpy(pool.data() + (size_t)rows[j] * R.ld, Vel + j * R.d, (size_t)R.d * 4);
+    HIPCHK(r, hipMemcpy(R.Vel, pool.data(), pool_bytes, hipMemcpyHostToDevice));
+    return RVEA_OK;
 }
 
 rvea_status rvea_get_counters(rvea_run r, rvea_counters *out)
@@ -1217,7 +1307,7 @@ rvea_status rvea_batch_admit(rvea_batch b, rvea_run r)
 {
     if (!b || !r) return RVEA_EINVAL;
     if (r->batch || r->phase != 0 || r->timing) return RVEA_ESTATE;
-    if (r->R.problem == kPolicy) return RVEA_EUNSUPPORTED;
+    if (r->R.problem == kPolicy || r->R.op != OP_GA) return RVEA_EUNSUPPORTED;
     if ((int)b->runs.size() >= b->max_runs) return RVEA_ENOMEM;
     // the run's pending work (creation, earlier generations) precedes the batch
     HIPCHK(r, hipStreamSynchronize(r->stream));

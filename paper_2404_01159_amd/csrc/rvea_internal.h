@@ -34,7 +34,10 @@ hipError_t launch_prepare(const RunView &R, hipStream_t s);
 // row stamps and per-block valid counts of the current population (after
 // initialization or a host-set state)
 hipError_t launch_stamp(const RunView &R, hipStream_t s);
+// reproduction and evaluation of the run's operator (the genetic kernels,
+// or launch_operator for the others)
 hipError_t launch_offspring(const RunView &R, hipStream_t s);
+hipError_t launch_operator(const RunView &R, hipStream_t s);  // DE, PSO, CSO, random
 hipError_t launch_assoc(const RunView &R, hipStream_t s);
 hipError_t launch_rerank(const RunView &R, hipStream_t s);
 hipError_t launch_select_back(const RunView &R, hipStream_t s);

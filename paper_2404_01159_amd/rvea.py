@@ -20,6 +20,8 @@ RVEA_OK, RVEA_EINVAL, RVEA_ENOMEM, RVEA_EDEVICE, RVEA_ESTATE, RVEA_EUNSUPPORTED 
 LINEAR_MULTIMODAL, SPHERE_UNIMODAL, SPHERE_MULTIMODAL = 1, 2, 3
 POLICY_LQ, POLICY_M, POLICY_D, POLICY_E = 100, 2, 6728, 16
 KERNEL_OFFSPRING, KERNEL_ASSOC, KERNEL_RERANK, KERNEL_GAMMA, KERNEL_ROLLOUT = 0, 1, 2, 3, 4
+OP_GA, OP_DE, OP_PSO, OP_CSO, OP_RAND = 0, 1, 2, 3, 4
+OPERATORS = {"ga": OP_GA, "de": OP_DE, "pso": OP_PSO, "cso": OP_CSO, "rand": OP_RAND}
 
 EXPORTS = [
     "rvea_default_params", "rvea_lattice_divisions", "rvea_footprint", "rvea_create",
@@ -28,6 +30,7 @@ EXPORTS = [
     "rvea_prepare_generations", "rvea_set_graphs",
     "rvea_get_state",
     "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
+    "rvea_operator_params", "rvea_get_velocities", "rvea_set_velocities",
     "rvea_get_counters",
     "rvea_set_timing", "rvea_kernel_time", "rvea_time_kernels", "rvea_autotune",
     "rvea_synchronize", "rvea_destroy",
@@ -43,8 +46,9 @@ EXPORTS = [
 class Params(C.Structure):
     _fields_ = [
         ("alpha", C.c_double), ("fr", C.c_double), ("t_max", C.c_int32),
-        ("reserved", C.c_int32), ("eta_c", C.c_double), ("eta_m", C.c_double),
+        ("op", C.c_int32), ("eta_c", C.c_double), ("eta_m", C.c_double),
         ("p_c", C.c_double), ("p_m", C.c_double), ("lb", C.c_double), ("ub", C.c_double),
+        ("op_a", C.c_double), ("op_b", C.c_double),
     ]
 
 
@@ -93,6 +97,9 @@ def _load():
         "rvea_get_offspring": [P, P, P, P],
         "rvea_get_selection": [P, P, P, P, P],
         "rvea_get_rows": [P, i32, P, i64, P, P],
+        "rvea_operator_params": [i32, P],
+        "rvea_get_velocities": [P, i32, P],
+        "rvea_set_velocities": [P, P],
         "rvea_get_counters": [P, P],
         "rvea_set_timing": [P, i32],
         "rvea_kernel_time": [P, i32, P, P],
@@ -138,9 +145,17 @@ def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-def default_params(**kw):
+def default_params(op=None, **kw):
+    """The defaults of rvea_default_params; ``op`` ("de", "pso", "cso", "rand"
+    or an id) selects a reproduction operator with its default parameters,
+    which keywords may then override."""
     p = Params()
     lib.rvea_default_params(C.byref(p))
+    if op is not None:
+        code = OPERATORS[op] if isinstance(op, str) else int(op)
+        st = lib.rvea_operator_params(code, C.byref(p))
+        if st != RVEA_OK:
+            raise RveaError(st, f"unknown operator {op!r}")
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -273,6 +288,19 @@ class Run:
         self._chk(lib.rvea_get_offspring(self._h, _p(X), _p(F), _p(parents)),
                   "rvea_get_offspring")
         return dict(X=X, F=F, parents=parents)
+
+    def get_velocities(self, offspring=False):
+        """Velocities of a PSO or CSO run: the slots' (K x d) or the last
+        offspring's (N x d)."""
+        V = np.zeros((self.N if offspring else self.K, self.d), np.float32)
+        self._chk(lib.rvea_get_velocities(self._h, 1 if offspring else 0, _p(V)),
+                  "rvea_get_velocities")
+        return V
+
+    def set_velocities(self, V):
+        V = np.ascontiguousarray(V, np.float32)
+        assert V.shape == (self.K, self.d)
+        self._chk(lib.rvea_set_velocities(self._h, _p(V)), "rvea_set_velocities")
 
     def get_selection(self):
         z = np.zeros(self.m, np.float32)

@@ -103,7 +103,6 @@ def check_generation(O, run, prm, st, off, sel, st2, stats, exact_survivors=Fals
     adapting generation V exact and gamma at 1e-13."""
     problem, m, d, N, K, seed = run.problem, run.m, run.d, run.N, run.K, run.seed
     op = ora_params(O, prm)
-    period = O.adapt_period(prm.fr, prm.t_max)
     t = st["t"] + 1
     assert st2["t"] == t
     parents, nv = O.mate(seed, t, st["valid"], N)
@@ -113,6 +112,16 @@ def check_generation(O, run, prm, st, off, sel, st2, stats, exact_survivors=Fals
     stats["straddles"] += gene_mismatches(off["X"], Xo, pre)
     stats["genes"] += Xo.size
     objectives_close(off["F"], O.evaluate(problem, m, off["X"]))
+    return check_after_offspring(O, run, prm, st, off, sel, st2, stats, exact_survivors)
+
+
+def check_after_offspring(O, run, prm, st, off, sel, st2, stats, exact_survivors=False):
+    """The rest of a generation once its offspring are checked: selection
+    from the GPU's merged objectives (Alg. 1), the new population, and the
+    adaptation (Alg. 2), as check_generation states."""
+    m, N, K = run.m, run.N, run.K
+    period = O.adapt_period(prm.fr, prm.t_max)
+    t = st["t"] + 1
     Fm = np.vstack([st["F"], off["F"]]).astype(np.float64)
     mv = np.concatenate([st["valid"], np.ones(N, np.uint8)])
     ref = O.select(m, K, N, t, prm.t_max, prm.alpha, Fm, mv, st["V"], st["gamma"])

@@ -64,9 +64,25 @@ def test_footprint_and_argument_checks(P):
         with pytest.raises(P.RveaError):
             P.footprint(*args)
     for kw in [dict(p_m=4.5), dict(p_m=-1.0), dict(lb=1.0, ub=1.0), dict(t_max=0),
-               dict(p_c=1.5), dict(fr=0.0), dict(reserved=3), dict(eta_c=-1.0)]:
+               dict(p_c=1.5), dict(fr=0.0), dict(op=5), dict(op=-1), dict(op_a=0.5),
+               dict(eta_c=-1.0)]:
         with pytest.raises(P.RveaError):
             P.footprint(1, 3, 12, 105, 105, P.default_params(**kw))
+    # operator parameters: ranges per operator, unused ones 0
+    for op, kw in [("de", dict(op_a=2.5)), ("de", dict(op_b=1.5)), ("pso", dict(op_a=1.5)),
+                   ("pso", dict(op_b=-0.1)), ("cso", dict(op_a=0.1)), ("rand", dict(op_b=1.0))]:
+        with pytest.raises(P.RveaError):
+            P.footprint(1, 3, 12, 105, 105, P.default_params(op, **kw))
+    with pytest.raises(P.RveaError):
+        P.default_params(7)
+    # the swarm operators add a velocity pool the size of the gene pool
+    ga = P.footprint(1, 3, 500, 105, 105)
+    for op in ("de", "rand"):
+        assert P.footprint(1, 3, 500, 105, 105, P.default_params(op)) <= ga
+    for op in ("pso", "cso"):
+        assert P.footprint(1, 3, 500, 105, 105, P.default_params(op)) >= ga + 210 * 512 * 4 - 256
+    de = P.default_params("de")
+    assert (de.op, de.op_a, de.op_b) == (1, 0.5, 0.9)
 
 
 def test_create_rejects_bad_workspace_before_touching_a_device(P):
