@@ -29,13 +29,29 @@ PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix
 WORKLOAD = "large_m3_d500_n10011"
 
 
+def operator_rows(op, N, K):
+    """Gene and velocity rows one reproduction launch reads and writes at
+    least: the rows each child (CSO: each pair) uses, counted once per use
+    but never beyond the K population rows they come from, and the
+    children's rows (genes, plus velocities for the swarms)."""
+    P = (N + 1) // 2
+    reads = {0: min(2 * P, K), 1: min(4 * N, K), 2: min(2 * N, K) + min(N, K),
+             3: 2 * min(2 * P, K), 4: 0}[op]
+    writes = {0: N, 1: N, 2: 2 * N, 3: 2 * N, 4: N}[op]
+    return reads, writes
+
+
 def kernel_work(name, run):
     """Algorithmic work of one launch: (unit, amount)."""
     N, K, d, m = run.N, run.K, run.d, run.m
     P = (N + 1) // 2
     if name == "offspring":
-        # read both parent rows of every pair, write every child row and its objectives
-        return "bytes", 2 * P * d * 4 + N * d * 4 + N * m * 4
+        op = int(run.params.op)
+        if op == 0:
+            # read both parent rows of every pair, write every child row and its objectives
+            return "bytes", 2 * P * d * 4 + N * d * 4 + N * m * 4
+        reads, writes = operator_rows(op, N, K)
+        return "bytes", (reads + writes) * d * 4 + N * m * 4
     if name == "assoc":
         # every (merged row, vector) pair: an m-term dot product (m fused
         # multiply-adds, 2m flops) and one max
@@ -285,6 +301,76 @@ def indicators_leg(a):
     return out
 
 
+def operators_leg(a):
+    """The extensibility study (Sec. 4): GA, DE, PSO, CSO and random
+    reproduction in the same RVEA.  On the policy workload, 50 generations
+    each from the same initial population: generations/s and the final
+    survivors' hypervolume and expected utility (normalised as in the policy
+    leg).  On the 10,011-vector workload: generations/s and the reproduction
+    kernel's time and HBM roofline per operator."""
+    import numpy as np
+    import torch
+
+    import paper_2404_01159_amd as P
+    from workloads import CONFIGS, POLICY_CONFIG as C, lq_system
+
+    out = {"operator_parameters": {"ga": "SBX + PM, eta 20, p_c 1, p_m 1",
+                                   "de": "DE/rand/1/bin F 0.5, CR 0.9",
+                                   "pso": "inertia 0.5, social 1.5", "cso": "phi 0",
+                                   "rand": "uniform in the box"}}
+    S = dict(lq_system(C["seed"], E=C["E"]), T=C["T"], sigma=C["sigma"])
+    W = weights_simplex(2, 99)
+    pol = {}
+    hi = None
+    for name in ("ga", "de", "pso", "cso", "rand"):
+        prm = P.default_params(name, t_max=C["gens"], lb=C["lb"], ub=C["ub"])
+        run = P.Run(C["problem"], C["m"], C["d"], C["N"], C["K"], seed=C["seed"], params=prm,
+                    system=S)
+        st0 = run.get_state(genes=False)
+        if hi is None:  # the same initial population for every operator
+            hi = st0["F"][st0["valid"] == 1].astype(np.float64).max(axis=0)
+        run.prepare(C["gens"])
+        run.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.run(C["gens"])
+        run.synchronize()
+        el = time.perf_counter() - t0
+        st = run.get_state(genes=False)
+        run.close()
+        pol[name] = dict(generations_per_s=C["gens"] / el,
+                         hypervolume_final=P.hypervolume(st["F"], st["valid"], [0.0, 0.0], hi),
+                         expected_utility_final=P.expected_utility(st["F"], W, st["valid"],
+                                                                   [0.0, 0.0], hi))
+    out["policy"] = dict(workload="4,096 policies (d=6,728), m=2, K=4,096, 16 rollouts x 200 "
+                                  "steps, 50 generations", per_operator=pol)
+    c = CONFIGS[WORKLOAD]
+    head = {}
+    for name in ("ga", "de", "pso", "cso", "rand"):
+        prm = P.default_params(name, t_max=c["gens"])
+        run = P.Run(c["problem"], c["m"], c["d"], c["N"], c["K"], seed=c["seed"], params=prm)
+        run.run(3)
+        gens = 20
+        run.prepare(gens)
+        run.synchronize()
+        t0 = time.perf_counter()
+        run.run(gens)
+        run.synchronize()
+        el = time.perf_counter() - t0
+        run.step()
+        t = run.time_kernels(TIMING_REPS)
+        run.select()
+        run.adapt()
+        run.synchronize()
+        r = roofline_of("offspring", run, t["offspring"], TIMING_REPS)
+        run.close()
+        head[name] = dict(generations_per_s=gens / el, offspring_us=t["offspring"] * 1e3,
+                          hbm_gbs=r["achieved"], hbm_frac=r["frac"],
+                          algorithmic_bytes=r["algorithmic_bytes"])
+    out[WORKLOAD] = head
+    return out
+
+
 def serving_legs(a):
     """Served runs (open loop, Poisson arrivals), the same runs all at once
     (batched capacity), and the same runs one at a time on the plain path."""
@@ -351,6 +437,8 @@ def main():
                     help="skip the policy-rollout (neuroevolution-shaped) workload")
     ap.add_argument("--no-sweeps", action="store_true",
                     help="skip the population-size and dimension sweeps")
+    ap.add_argument("--no-operators", action="store_true",
+                    help="skip the reproduction-operator comparison")
     ap.add_argument("--no-indicators", action="store_true",
                     help="skip the hypervolume / expected-utility leg")
     ap.add_argument("--serve-runs", type=int, default=256)
@@ -449,6 +537,10 @@ def main():
     if not a.no_indicators:
         indicators = indicators_leg(a)
 
+    operators = None
+    if not a.no_operators:
+        operators = operators_leg(a)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(cfg, a.cpu_budget)
@@ -479,6 +571,7 @@ def main():
         "policy": policy,
         "sweeps": sweeps,
         "indicators": indicators,
+        "operators": operators,
     }
     print(json.dumps(out), flush=True)
 
