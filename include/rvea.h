@@ -212,6 +212,15 @@ rvea_status rvea_prepare_generations(rvea_run run, int n);
  * launches every kernel individually. */
 rvea_status rvea_set_graphs(rvea_run run, int enable);
 
+/* Association (Alg. 1, Eq. 2) through an index of the reference vectors
+ * (1, the default for m = 3) or by a scan of all K vectors per row (0).
+ * Both give the same association, angle and APD for every row: the index
+ * hands each row a candidate list that holds its vector of largest cosine
+ * and every vector tied with it, and the cosines are computed the same way.
+ * The index is rebuilt whenever V changes.  RVEA_EUNSUPPORTED to enable it
+ * for m != 3; only between generations and outside a batch (RVEA_ESTATE). */
+rvea_status rvea_set_index(rvea_run run, int enable);
+
 /* Copies the run state to host memory (waits for the stream).  Any pointer
  * may be NULL.  Layouts, row-major: X K x d float, F K x m float,
  * valid K bytes (1 = slot holds an individual), V and V0 K x m double,

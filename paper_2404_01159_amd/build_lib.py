@@ -13,8 +13,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librvea.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["k_gen.hip", "k_ops.hip", "k_select.hip", "k_vectors.hip", "k_policy.hip",
-           "rvea_host.hip", "rvea_indicators.hip"]
+SOURCES = ["k_gen.hip", "k_ops.hip", "k_select.hip", "k_grid.hip", "k_vectors.hip",
+           "k_policy.hip", "rvea_host.hip", "rvea_indicators.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",

@@ -1,0 +1,723 @@
+// k_grid.hip -- association (Alg. 1, Eq. 2) through an index of the
+// reference vectors, three objectives.
+//
+// The association of a row is the vector of largest cosine (lowest index on
+// ties).  Here each row looks only at a short candidate list that provably
+// holds that vector and every vector tied with it, and computes the binary64
+// cosines of those candidates exactly as the full re-rank does, so the
+// result is the same as a scan of all K vectors.
+//
+// Index.  A direction x >= 0 is mapped to the simplex point q of x / r
+// (componentwise; r > 0 is the range vector of the last adaptation, scaled
+// to max 1, so that the adapted lattice is again a uniform lattice in q) and
+// q (its first two coordinates) to a cell of a G x G grid over [0, 1]^2.  A
+// cell C is the square clipped to the simplex, a polygon of at most five
+// vertices; the directions of the rows that land in C form the cone over
+// that polygon (up to rounding).  Distances between directions are chord
+// lengths |u - v| of unit vectors (a metric, monotone in the angle), so no
+// inverse trigonometric function is needed.  For each cell, built whenever
+// V changes:
+//   u_c    the unit direction of the polygon's vertex mean; rho the largest
+//          distance from u_c to a vertex (the largest to any point of the
+//          cell: the distance to a fixed direction is quasi-convex on the
+//          plane of q, so its maximum over the polygon is at a vertex)
+//   b      an upper bound of the distance from any point of C to its nearest
+//          vector: min over the vectors k of the cells around C of the largest
+//          distance from a vertex to v_k (again attained at a vertex)
+//   box    the smallest square of cells around C whose boundary (clipped to
+//          the simplex) is farther than b + rho from u_c: that ball around
+//          u_c is convex in q, so it lies inside the box
+//   P      the vectors in the box whose distance to the cell is at most b
+//          (the least over its edges, each the distance to a great-circle
+//          arc; the cell's own vectors always): any vector that is the
+//          nearest for some row direction in C is within b of it
+//   list   P without the vectors that a champion (the vector of largest
+//          cosine at a vertex or at u_c) beats at every vertex by more than
+//          1e-12: the cosine difference is linear on the cone, so such a
+//          vector loses to the champion for every row direction in C, with
+//          a margin far above binary64 rounding
+// Lists longer than kSlot, cells whose box would pass kStage cells from
+// C, and cells with no vector within kNear cells are marked for a full scan
+// (correct for any vector set, counted as full rescans).  Each cell's list
+// has a slot of kSlot records of its own; the cells' ranges of vector
+// positions are allocated by one atomic add per wavefront, so the order of
+// the vectors in memory varies from build to build (no result depends on it).
+#include "rvea_dev.h"
+#include "rvea_internal.h"
+
+namespace rvea {
+
+constexpr int kSlot = 24;      // list records per cell (longer lists: a full scan)
+constexpr int kChamps = 6;     // champions per cell: five vertices and the centre
+constexpr int kGridRowLanes = 4;  // lanes per row of the association
+constexpr double kDomMargin = 1e-12;
+
+struct D3 {
+    double x, y, z;
+};
+__device__ __forceinline__ D3 d3(double x, double y, double z) { return D3{x, y, z}; }
+__device__ __forceinline__ double dot3(const D3 &a, const D3 &b)
+{
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+__device__ __forceinline__ D3 sub3(const D3 &a, const D3 &b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ D3 unit3(const D3 &a)
+{
+    const double inv = 1.0 / sqrt(dot3(a, a));
+    return d3(a.x * inv, a.y * inv, a.z * inv);
+}
+
+// Binary32 versions for the geometric tests of the build.  Those tests only
+// have to keep every possible candidate, so they run in single precision
+// with hardware square root and reciprocal (1 ulp) and a slack kSlack on
+// every comparison, far above their rounding (chords of unit vectors in
+// [0, 2], each off by well under 1e-6); the tests that decide exclusion
+// for good (domination) stay in binary64.
+constexpr float kSlack = 4e-6f;
+struct F3 {
+    float x, y, z;
+};
+__device__ __forceinline__ F3 f3(float x, float y, float z) { return F3{x, y, z}; }
+__device__ __forceinline__ F3 f3of(const D3 &a) { return F3{(float)a.x, (float)a.y, (float)a.z}; }
+__device__ __forceinline__ float fdot(const F3 &a, const F3 &b)
+{
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+__device__ __forceinline__ F3 fsub(const F3 &a, const F3 &b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ F3 fcross(const F3 &a, const F3 &b)
+{
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ F3 funit(const F3 &a)
+{
+    const float inv = __builtin_amdgcn_rcpf(fsqrt(fdot(a, a)));
+    return f3(a.x * inv, a.y * inv, a.z * inv);
+}
+__device__ __forceinline__ float fchord(const F3 &a, const F3 &b)
+{
+    const F3 d = fsub(a, b);
+    return fsqrt(fdot(d, d));
+}
+__device__ float farc_chord(const F3 &u, const F3 &a, const F3 &b, const F3 &n, bool valid)
+{
+    const float ends = fminf(fchord(u, a), fchord(u, b));
+    if (!valid) return ends;
+    const float un = fdot(u, n);
+    const F3 w = f3(u.x - un * n.x, u.y - un * n.y, u.z - un * n.z);
+    const float wn = fsqrt(fdot(w, w));
+    if (wn > 0.0f && fdot(fcross(a, w), n) >= 0.0f && fdot(fcross(w, b), n) >= 0.0f)
+        return fminf(ends, fsqrt(2.0f * un * un * __builtin_amdgcn_rcpf(1.0f + wn)));
+    return ends;
+}
+__device__ float farc_chord_of(const F3 &u, const F3 &A, const F3 &B)
+{
+    const F3 a = funit(A), b = funit(B);
+    const F3 n = fcross(a, b);
+    const float nn = fsqrt(fdot(n, n));
+    const bool valid = nn > 1e-30f;
+    const float inv = valid ? __builtin_amdgcn_rcpf(nn) : 0.0f;
+    return farc_chord(u, a, b, f3(n.x * inv, n.y * inv, n.z * inv), valid);
+}
+__device__ __forceinline__ F3 flift(float q1, float q2, const double *r)
+{
+    return f3((float)r[0] * q1, (float)r[1] * q2, (float)r[2] * (1.0f - q1 - q2));
+}
+
+// the direction of simplex point (q1, q2) scaled back by r
+__device__ __forceinline__ D3 lift(double q1, double q2, const double *r)
+{
+    return d3(r[0] * q1, r[1] * q2, r[2] * (1.0 - q1 - q2));
+}
+
+// cell of a direction x >= 0 (x != 0); q pulled onto the simplex if rounding
+// left it just outside.  -1 if the coordinates are not finite.
+__device__ __forceinline__ int cell_of(double x0, double x1, double x2, const double *r, int G)
+{
+    const double y0 = x0 / r[0], y1 = x1 / r[1], y2 = x2 / r[2];
+    const double s = y0 + y1 + y2;
+    double q1 = y0 / s, q2 = y1 / s;
+    if (!(q1 >= 0.0 && q2 >= 0.0 && q1 <= 2.0 && q2 <= 2.0)) return -1;
+    const double t = q1 + q2;
+    if (t > 1.0) {
+        q1 /= t;
+        q2 /= t;
+    }
+    int ci = (int)floor(q1 * G), cj = (int)floor(q2 * G);
+    ci = ci < 0 ? 0 : (ci > G - 1 ? G - 1 : ci);
+    cj = cj < 0 ? 0 : (cj > G - 1 ? G - 1 : cj);
+    return ci * G + cj;
+}
+
+// One cell's geometry, held in LDS by the cell's workgroup: the square
+// [a, a+h] x [b, b+h] clipped to q1 + q2 <= 1 as five vertices in order
+// (with corner sums s0 <= s1 = s3 <= s2: the whole square when s2 <= 1, a
+// pentagon when only the far corner is cut, a triangle (or a point) when
+// s1 > 1; fewer distinct vertices repeat the last, which adds only
+// zero-length edges), their unit directions in binary64 (champions and
+// domination) and binary32 (the geometric tests), the unit normals of the
+// edges' planes, u_c and rho.
+constexpr int kNv = 5;
+struct CellGeo {
+    double X[kNv][3];
+    float Xf[kNv][3], Nf[kNv][3];
+    int nok[kNv];
+    double uc[3];
+    float ucf[3];
+    float rho;
+};
+
+__device__ __forceinline__ F3 ld3(const float (&a)[3]) { return f3(a[0], a[1], a[2]); }
+__device__ __forceinline__ D3 ld3(const double (&a)[3]) { return d3(a[0], a[1], a[2]); }
+
+// the cell's vertex v (v < kNv) in q, for a cell (ci, cj) with ci + cj <= G
+// (its corner (a, b) on or below the diagonal; at ci + cj = G all five are
+// that corner, up to rounding)
+__device__ __forceinline__ void cell_vertex(int G, int c, int v, double &px, double &py)
+{
+    const double h = 1.0 / G;
+    const double a = (c / G) * h, b = (c % G) * h;
+    const double s1 = a + h + b, s2 = a + b + 2.0 * h;
+    if (s2 <= 1.0) {  // the whole square
+        const double x[kNv] = {a, a + h, a + h, a, a}, y[kNv] = {b, b, b + h, b + h, b + h};
+        px = x[v];
+        py = y[v];
+    } else if (s1 <= 1.0) {  // the corner (a+h, b+h) cut off
+        const double x[kNv] = {a, a + h, a + h, 1.0 - b - h, a};
+        const double y[kNv] = {b, b, 1.0 - a - h, b + h, b + h};
+        px = x[v];
+        py = y[v];
+    } else {  // only the corner (a, b) inside
+        const double x[kNv] = {a, 1.0 - b, a, a, a}, y[kNv] = {b, b, 1.0 - a, 1.0 - a, 1.0 - a};
+        px = x[v];
+        py = y[v];
+    }
+}
+
+// the geometry of a live cell, by the workgroup: lanes 0..4 the vertices,
+// lane 5 u_c; then lanes 0..4 the edge normals and rho (g.rho as the bits
+// of a non-negative float, combined by an LDS max)
+__device__ void cell_geo(const RunView &R, int c, CellGeo &g, int lane)
+{
+    if (lane <= kNv) {
+        double px = 0.0, py = 0.0;
+        if (lane < kNv) {
+            cell_vertex(R.gG, c, lane, px, py);
+        } else {
+            for (int v = 0; v < kNv; ++v) {
+                double x, y;
+                cell_vertex(R.gG, c, v, x, y);
+                px += x;
+                py += y;
+            }
+            px /= kNv;
+            py /= kNv;
+        }
+        const D3 X = unit3(lift(px, py, R.gr));
+        const F3 Xf = f3of(X);
+        double *dst = lane < kNv ? g.X[lane] : g.uc;
+        float *dsf = lane < kNv ? g.Xf[lane] : g.ucf;
+        dst[0] = X.x;
+        dst[1] = X.y;
+        dst[2] = X.z;
+        dsf[0] = Xf.x;
+        dsf[1] = Xf.y;
+        dsf[2] = Xf.z;
+    }
+    if (lane == 0) g.rho = 0.0f;
+    __syncthreads();
+    if (lane < kNv) {
+        const F3 p = ld3(g.Xf[lane]), q = ld3(g.Xf[(lane + 1) % kNv]);
+        const F3 n = fcross(p, q);
+        const float nn = fsqrt(fdot(n, n));
+        g.nok[lane] = nn > 1e-30f;
+        const float inv = g.nok[lane] ? __builtin_amdgcn_rcpf(nn) : 0.0f;
+        g.Nf[lane][0] = n.x * inv;
+        g.Nf[lane][1] = n.y * inv;
+        g.Nf[lane][2] = n.z * inv;
+        atomicMax(reinterpret_cast<unsigned int *>(&g.rho),
+                  __float_as_uint(fchord(ld3(g.ucf), p)));
+    }
+    __syncthreads();
+}
+
+// least distance from unit v to the cell (v outside it: the least over the
+// polygon's edges, each an arc of a great circle)
+__device__ float cell_dist(const CellGeo &g, const F3 &v)
+{
+    float d = INFINITY;
+    for (int e = 0; e < kNv; ++e)
+        d = fminf(d, farc_chord(v, ld3(g.Xf[e]), ld3(g.Xf[(e + 1) % kNv]), ld3(g.Nf[e]),
+                                g.nok[e] != 0));
+    return d;
+}
+
+__device__ __forceinline__ D3 gvh_at(const RunView &R, int64_t p)
+{
+    const double4 v = reinterpret_cast<const double4 *>(R.gvh)[p];
+    return d3(v.x, v.y, v.z);
+}
+
+// a vector of the box belongs to P (cell c's own vectors always do); b
+// already holds its slack
+__device__ __forceinline__ bool in_p(const CellGeo &g, const D3 &v, bool own, float b)
+{
+    if (own) return true;
+    const F3 vf = f3of(v);
+    // a lower bound of the distance first
+    if (fchord(ld3(g.ucf), vf) - g.rho - 2.0f * kSlack > b) return false;
+    return cell_dist(g, vf) - kSlack <= b;
+}
+
+// the champions of a cell (LDS): unit directions and vector ids (-1: none)
+struct Champs {
+    double v[kChamps][3];
+    int32_t j[kChamps];
+};
+
+// some champion beats v at every vertex by more than the margin
+__device__ __forceinline__ bool dominated(const CellGeo &g, const Champs &ch, const D3 &v, int32_t j)
+{
+    for (int d = 0; d < kChamps; ++d) {
+        if (ch.j[d] < 0 || ch.j[d] == j) continue;
+        const D3 w = sub3(ld3(ch.v[d]), v);
+        bool all = true;
+        for (int e = 0; e < kNv; ++e) all = all && dot3(ld3(g.X[e]), w) > kDomMargin;
+        if (all) return true;
+    }
+    return false;
+}
+
+// first position of a range of n items allocated by the whole wavefront
+// with one atomic add on *total (every lane active; lanes without items pass 0)
+__device__ __forceinline__ int64_t wave_alloc(int n, unsigned long long *total)
+{
+    const int incl = wave_incl_scan(n);
+    const int sum = __builtin_amdgcn_readlane(incl, 63);
+    unsigned long long base = 0;
+    if ((threadIdx.x & 63) == 0 && sum > 0) base = atomicAdd(total, (unsigned long long)sum);
+    base = __shfl(base, 0, 64);
+    return (int64_t)base + incl - n;
+}
+
+// ------------------------------------------------------------- build
+// vectors per cell (counts start at zero: the last build cleared them)
+__global__ __launch_bounds__(256) void k_grid_bucket(RunView R, int gate)
+{
+    if (!gate && *R.vchanged == 0) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= R.K) return;
+    int c = cell_of(R.V[j * 3], R.V[j * 3 + 1], R.V[j * 3 + 2], R.gr, R.gG);
+    if (c < 0) c = 0;  // cannot happen for a nonzero vector >= 0
+    R.gcell[j] = c;
+    atomicAdd(&R.gcnt[c], 1);
+}
+
+// each cell's range of positions (one atomic add per wavefront); the
+// counts become the fill cursors
+__global__ __launch_bounds__(256) void k_grid_ranges(RunView R, int gate)
+{
+    if (!gate && *R.vchanged == 0) return;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t cells = (int64_t)R.gG * R.gG;
+    const int n = c < cells ? R.gcnt[c] : 0;
+    const int64_t st = wave_alloc(n, &R.gtot[0]);
+    if (c < cells) {
+        R.gstart[c] = (int32_t)st;
+        R.gnum[c] = n;
+        R.gcnt[c] = 0;
+    }
+}
+
+// vectors into their cells' ranges, with their unit directions
+__global__ __launch_bounds__(256) void k_grid_fill(RunView R, int gate)
+{
+    if (!gate && *R.vchanged == 0) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= R.K) return;
+    const int c = R.gcell[j];
+    const int64_t p = R.gstart[c] + atomicAdd(&R.gcnt[c], 1);
+    R.gvec[p] = (int32_t)j;
+    const double inv = 1.0 / R.vn[j];
+    reinterpret_cast<double4 *>(R.gvh)[p] =
+        make_double4(R.V[j * 3] * inv, R.V[j * 3 + 1] * inv, R.V[j * 3 + 2] * inv, 0.0);
+}
+
+// wavefront-wide minimum / sum / best (largest value, lowest id on ties)
+// over the 64 lanes (every lane active)
+__device__ __forceinline__ double wave_fmin(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_imin(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ void wave_best(double &v, int32_t &j, int32_t &p)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int32_t oj = __shfl_xor(j, o, 64), op = __shfl_xor(p, o, 64);
+        if (ov > v || (ov == v && oj < j)) {
+            v = ov;
+            j = oj;
+            p = op;
+        }
+    }
+}
+
+constexpr int kNear = 3;  // the covering search looks at the (2 kNear + 1)^2 cells around
+
+// The vectors of the (2 kStage + 1)^2 cells around a cell, staged in LDS by
+// its workgroup: unit direction, id, raw vector and norm (the list record),
+// and the cell offset.  kStageCap entries at most.
+constexpr int kStage = 4;
+constexpr int kStageW = 2 * kStage + 1;
+constexpr int kStageCap = 192;
+struct Stage {
+    double vh[kStageCap][3];
+    double rec[kStageCap][4];
+    int32_t j[kStageCap];
+    int8_t di[kStageCap], dj[kStageCap];
+    int n;
+};
+
+// One wavefront per cell: the neighbourhood staged in LDS; b from the
+// cells within kNear; the box radius (lane k tests radius k, at most
+// kStage); the champions and the list from the staged box vectors, written
+// into the cell's slot at each lane's prefix.
+// A neighbourhood over kStageCap vectors or a box over kStage marks the cell
+// for a full scan.  Also clears the cell's fill cursor and the range
+// allocator for the next build.
+__global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
+{
+    if (!gate && *R.vchanged == 0) return;
+    const int G = R.gG;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (c >= G * G) return;  // uniform
+    __shared__ CellGeo g;
+    __shared__ Champs ch;
+    __shared__ Stage st;
+    const int ci = c / G, cj = c % G;
+    if (lane == 0) {
+        if (c == 0) R.gtot[0] = 0;
+        R.gcnt[c] = 0;
+    }
+    if (ci + cj > G) {  // outside the simplex (corner sum above 1): no row lands here
+        if (lane == 0) {
+            R.lstart[c] = 0;
+            R.lcnt[c] = 0;
+        }
+        return;  // uniform
+    }
+    // stage: each lane's cells of the neighbourhood, their vector counts
+    // scanned over the wave, then the vectors
+    int cnt[2] = {0, 0}, from[2] = {0, 0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int t = lane + 64 * u;
+        if (t < kStageW * kStageW) {
+            const int i = ci - kStage + t / kStageW, jj = cj - kStage + t % kStageW;
+            if (i >= 0 && i < G && jj >= 0 && jj < G) {
+                from[u] = R.gstart[i * G + jj];
+                cnt[u] = R.gnum[i * G + jj];
+            }
+        }
+    }
+    const int mine0 = cnt[0] + cnt[1];
+    const int incl0 = wave_incl_scan(mine0);
+    const int nst = __builtin_amdgcn_readlane(incl0, 63);
+    cell_geo(R, c, g, lane);
+    bool full = nst > kStageCap;
+    if (!full) {
+        int q = incl0 - mine0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int t = lane + 64 * u;
+            for (int k = 0; k < cnt[u]; ++k, ++q) {
+                const int p = from[u] + k;
+                const int32_t j = R.gvec[p];
+                const D3 v = gvh_at(R, p);
+                st.vh[q][0] = v.x;
+                st.vh[q][1] = v.y;
+                st.vh[q][2] = v.z;
+                st.j[q] = j;
+                st.di[q] = (int8_t)(t / kStageW - kStage);
+                st.dj[q] = (int8_t)(t % kStageW - kStage);
+                st.rec[q][0] = R.V[(int64_t)j * 3];
+                st.rec[q][1] = R.V[(int64_t)j * 3 + 1];
+                st.rec[q][2] = R.V[(int64_t)j * 3 + 2];
+                st.rec[q][3] = R.vn[j];
+            }
+        }
+    }
+    __syncthreads();
+    // b: the best covering vector among the cells within kNear
+    float best = INFINITY;
+    if (!full) {
+        for (int q = lane; q < nst; q += 64) {
+            if (abs(st.di[q]) > kNear || abs(st.dj[q]) > kNear) continue;
+            const F3 v = f3(st.vh[q][0], st.vh[q][1], st.vh[q][2]);
+            float cov = 0.0f;
+            for (int e = 0; e < kNv; ++e) cov = fmaxf(cov, fchord(ld3(g.Xf[e]), v));
+            best = fminf(best, cov);
+        }
+    }
+    best = (float)wave_fmin((double)best);
+    full = full || !(best < INFINITY);
+    const float b = best + kSlack;
+    int kc = 0x7fffffff;
+    if (!full) {  // lane k: does the box of radius k hold the ball of radius b + rho?
+        const int k = lane;
+        bool ok = false;
+        if (k <= kStage) {
+            const int i0 = max(0, ci - k), i1 = min(G - 1, ci + k);
+            const int j0 = max(0, cj - k), j1 = min(G - 1, cj + k);
+            // the sides are exact grid lines in binary64 (their ends on the
+            // simplex's edge), lifted in binary32; the slack covers both
+            const double h = 1.0 / G;
+            const float rad = b + g.rho + 2.0f * kSlack;
+            const F3 ucf = ld3(g.ucf);
+            float lo = INFINITY;
+            if (i0 > 0) {
+                const double x = i0 * h, ya = j0 * h, yb = fmin((j1 + 1) * h, 1.0 - x);
+                if (yb >= ya)
+                    lo = fminf(lo, farc_chord_of(ucf, flift((float)x, (float)ya, R.gr),
+                                                 flift((float)x, (float)yb, R.gr)));
+            }
+            if (i1 < G - 1) {
+                const double x = (i1 + 1) * h, ya = j0 * h, yb = fmin((j1 + 1) * h, 1.0 - x);
+                if (yb >= ya)
+                    lo = fminf(lo, farc_chord_of(ucf, flift((float)x, (float)ya, R.gr),
+                                                 flift((float)x, (float)yb, R.gr)));
+            }
+            if (j0 > 0) {
+                const double y = j0 * h, xa = i0 * h, xb = fmin((i1 + 1) * h, 1.0 - y);
+                if (xb >= xa)
+                    lo = fminf(lo, farc_chord_of(ucf, flift((float)xa, (float)y, R.gr),
+                                                 flift((float)xb, (float)y, R.gr)));
+            }
+            if (j1 < G - 1) {
+                const double y = (j1 + 1) * h, xa = i0 * h, xb = fmin((i1 + 1) * h, 1.0 - y);
+                if (xb >= xa)
+                    lo = fminf(lo, farc_chord_of(ucf, flift((float)xa, (float)y, R.gr),
+                                                 flift((float)xb, (float)y, R.gr)));
+            }
+            ok = lo > rad;
+        }
+        kc = wave_imin(ok ? k : 0x7fffffff);
+        full = kc == 0x7fffffff;
+    }
+    if (!full) {
+        // members of P among this lane's staged entries (q = lane + 64 u),
+        // and the champions: largest cosine at each vertex and at u_c
+        uint32_t mem = 0;
+        double bv[kChamps];
+        int32_t bj[kChamps], bq[kChamps];
+#pragma unroll
+        for (int d = 0; d < kChamps; ++d) {
+            bv[d] = -INFINITY;
+            bj[d] = 0x7fffffff;
+            bq[d] = -1;
+        }
+        for (int u = 0; lane + 64 * u < nst; ++u) {
+            const int q = lane + 64 * u;
+            if (abs(st.di[q]) > kc || abs(st.dj[q]) > kc) continue;
+            const D3 v = ld3(st.vh[q]);
+            if (!in_p(g, v, st.di[q] == 0 && st.dj[q] == 0, b)) continue;
+            mem |= 1u << u;
+            const int32_t j = st.j[q];
+#pragma unroll
+            for (int d = 0; d < kChamps; ++d) {
+                const double cv = dot3(d < kNv ? ld3(g.X[d]) : ld3(g.uc), v);
+                if (cv > bv[d] || (cv == bv[d] && j < bj[d])) {
+                    bv[d] = cv;
+                    bj[d] = j;
+                    bq[d] = q;
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < kChamps; ++d) wave_best(bv[d], bj[d], bq[d]);
+        if (lane < kChamps) {
+            int32_t q = -1;
+#pragma unroll
+            for (int d = 0; d < kChamps; ++d) q = lane == d ? bq[d] : q;
+            ch.j[lane] = q < 0 ? -1 : st.j[q];
+            ch.v[lane][0] = q < 0 ? 0.0 : st.vh[q][0];
+            ch.v[lane][1] = q < 0 ? 0.0 : st.vh[q][1];
+            ch.v[lane][2] = q < 0 ? 0.0 : st.vh[q][2];
+        }
+        __syncthreads();
+        // the list: members no champion beats on the whole cell
+        uint32_t keep = 0;
+        int mine = 0;
+        for (int u = 0; lane + 64 * u < nst; ++u) {
+            const int q = lane + 64 * u;
+            if (((mem >> u) & 1u) && !dominated(g, ch, ld3(st.vh[q]), st.j[q])) {
+                keep |= 1u << u;
+                ++mine;
+            }
+        }
+        const int incl = wave_incl_scan(mine);
+        const int n = __builtin_amdgcn_readlane(incl, 63);
+        full = n > kSlot;
+        // the cell's records in its own slot, each lane at its prefix
+        const int64_t base = (int64_t)c * kSlot;
+        if (!full) {
+            int64_t o = base + incl - mine;
+            for (int u = 0; lane + 64 * u < nst; ++u) {
+                if (!((keep >> u) & 1u)) continue;
+                const int q = lane + 64 * u;
+                reinterpret_cast<double4 *>(R.lrec)[o] =
+                    make_double4(st.rec[q][0], st.rec[q][1], st.rec[q][2], st.rec[q][3]);
+                R.lidx[o] = st.j[q];
+                ++o;
+            }
+            if (lane == 0) {
+                R.lstart[c] = (int32_t)base;
+                R.lcnt[c] = n;
+            }
+        }
+    }
+    if (full && lane == 0) {
+        R.lstart[c] = -1;
+        R.lcnt[c] = -1;
+    }
+}
+
+// ----------------------------------------------------------- association
+// kGridRowLanes lanes per merged row: f' = F - z* in binary64 and |f'| as
+// the re-rank forms them, the row's cell, the binary64 cosines of the
+// cell's list (or of every vector for a cell marked for a full scan), the
+// best with the lowest index on ties, then as the re-rank: angle, APD of
+// Eq. 4 and the per-vector minimum of (APD, row).
+__global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
+{
+    const int sub = threadIdx.x % kGridRowLanes;
+    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kGridRowLanes;
+    const bool in = i < R.M;
+    const int64_t pop = *R.t_done;
+    const uint32_t *zb = zbuf(R, pop + 1);
+    const float *Fm = fm_of(R, pop);
+    float rf[3] = {0.f, 0.f, 0.f};
+    if (in)
+        for (int k = 0; k < 3; ++k) rf[k] = Fm[i * 3 + k];
+    const bool act = in && R.mvalid[i];
+    double f[3];
+    for (int k = 0; k < 3; ++k) {
+        const float zk = ord_dec(zb[k]);
+        f[k] = act ? (double)rf[k] - (double)zk : 0.0;
+    }
+    double n2 = f[0] * f[0];
+    n2 = fma(f[1], f[1], n2);
+    n2 = fma(f[2], f[2], n2);
+    const double nrm = sqrt(n2);
+    const bool live = act && nrm > 0.0;
+    int32_t st = -1, n = 0;
+    if (live) {
+        const int c = cell_of(f[0], f[1], f[2], R.gr, R.gG);
+        if (c >= 0) {
+            st = R.lstart[c];
+            n = R.lcnt[c];
+        }
+    }
+    const bool full = live && (st < 0 || n <= 0);
+    double best = -INFINITY;
+    int64_t bj = R.K;
+    if (live && !full) {
+        const double4 *rec = reinterpret_cast<const double4 *>(R.lrec) + st;
+        for (int e = sub; e < n; e += kGridRowLanes) {
+            const double4 v = rec[e];
+            const int64_t j = R.lidx[st + e];
+            double s = f[0] * v.x;
+            s = fma(f[1], v.y, s);
+            s = fma(f[2], v.z, s);
+            const double cv = s / (nrm * v.w);
+            if (cv > best || (cv == best && j < bj)) {
+                best = cv;
+                bj = j;
+            }
+        }
+    } else if (full) {
+        for (int64_t j = sub; j < R.K; j += kGridRowLanes) {
+            double s = f[0] * R.V[j * 3];
+            s = fma(f[1], R.V[j * 3 + 1], s);
+            s = fma(f[2], R.V[j * 3 + 2], s);
+            const double cv = s / (nrm * R.vn[j]);
+            if (cv > best || (cv == best && j < bj)) {
+                best = cv;
+                bj = j;
+            }
+        }
+    }
+    // the row's lanes are adjacent: combine them (every lane active)
+#pragma unroll
+    for (int o = 1; o < kGridRowLanes; o <<= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int64_t oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && oj < bj)) {
+            best = ob;
+            bj = oj;
+        }
+    }
+    if (!in || sub != 0) return;
+    if (!act) {
+        R.assoc[i] = -1;
+        R.apd[i] = INFINITY;
+        return;
+    }
+    if (!live) {  // the row is the ideal point: vector 0, APD 0
+        R.assoc[i] = 0;
+        R.apd[i] = 0.0;
+        atomicMin(&R.key[0], (unsigned long long)i);
+        return;
+    }
+    if (full) atomicAdd(&R.counters[1], 1ull);
+    const double gj = bj < R.K ? R.gamma[bj] : R.gamma[0];
+    if (bj >= R.K) bj = 0;
+    const double cc = best > 1.0 ? 1.0 : (best < -1.0 ? -1.0 : best);
+    const double th = acos(cc);
+    const double a = (1.0 + *R.pen * th / gj) * nrm;
+    R.assoc[i] = (int32_t)bj;
+    R.apd[i] = a;
+    const unsigned long long ab = (unsigned long long)__double_as_longlong(a);
+    atomicMin(&R.key[bj], ((ab >> R.kb) << R.kb) | (unsigned long long)i);
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force)
+{
+    if (R.gG <= 0) return hipSuccess;
+    const unsigned vb = (unsigned)((R.K + 255) / 256);
+    const int64_t cells = (int64_t)R.gG * R.gG;
+    k_grid_bucket<<<vb, 256, 0, s>>>(R, force);
+    k_grid_ranges<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(R, force);
+    k_grid_fill<<<vb, 256, 0, s>>>(R, force);
+    k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_assoc_grid(const RunView &R, hipStream_t s)
+{
+    const int64_t threads = R.M * kGridRowLanes;
+    k_assoc_grid<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(R);
+    return hipGetLastError();
+}
+
+int grid_slot() { return kSlot; }
+
+int grid_side(int m, int64_t K)
+{
+    if (m != 3) return 0;
+    int G = (int)ceil(1.4 * sqrt((double)K));
+    return G < 2 ? 2 : G;
+}
+
+}  // namespace rvea

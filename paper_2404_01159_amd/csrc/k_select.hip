@@ -826,6 +826,7 @@ static void assoc_launch(const RunView &R, hipStream_t s, int gate)
 
 hipError_t launch_assoc(const RunView &R, hipStream_t s)
 {
+    if (R.gG > 0) return launch_assoc_grid(R, s);  // indexed: the re-rank is folded in
     assoc_launch<false>(R, s, 1);
     return hipGetLastError();
 }
@@ -847,6 +848,7 @@ static void rerank_launch(const RunView &R, hipStream_t s, int gate)
 
 hipError_t launch_rerank(const RunView &R, hipStream_t s)
 {
+    if (R.gG > 0) return hipSuccess;
     rerank_launch<false>(R, s, 1);
     return hipGetLastError();
 }

@@ -98,6 +98,11 @@ __device__ __forceinline__ void adapt_v_body(const RunView &R, int64_t bx, bool 
         ok = ok && r[k] > 0.0 && isfinite(r[k]);
     }
     if (j == 0) *R.vchanged = ok ? 1 : 0;
+    if (j == 0 && ok && R.gr) {  // the index's scaling: r over its maximum, at least 1e-6
+        double mx = r[0];
+        for (int k = 1; k < R.m; ++k) mx = fmax(mx, r[k]);
+        for (int k = 0; k < R.m; ++k) R.gr[k] = fmax(r[k] / mx, 1e-6);
+    }
     if (!ok || j >= R.K) return;
     double w[kMaxM];
     for (int k = 0; k < R.m; ++k) w[k] = R.V0[j * R.m + k] * r[k];
@@ -195,7 +200,9 @@ hipError_t launch_adapt(const RunView &R, hipStream_t s)
     k_adapt_v<<<blocks(R.K, 256), 256, 0, s>>>(R);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_gamma(R, s, 0);
+    e = launch_gamma(R, s, 0);
+    if (e != hipSuccess) return e;
+    return launch_grid_build(R, s, 0);
 }
 
 }  // namespace rvea

@@ -58,6 +58,21 @@ struct RunView {
     int op;             // reproduction operator (OP_*)
     double op_a, op_b;  // its parameters
     float *Vel;         // (K+N) x ld velocities by physical row (PSO, CSO), else null
+    // index of the reference vectors (three objectives; k_grid.hip)
+    int gG;             // cells per side of the grid (0: association by full scan)
+    int64_t gcap;       // list records: a slot of equal size per cell
+    double *gr;         // 3: the scaling r the grid's coordinates divide by
+    int32_t *gcell;     // K: cell of each vector
+    int32_t *gcnt;      // G*G: vectors per cell, then fill cursors (build)
+    int32_t *gstart;    // G*G: first position of each cell's vectors
+    int32_t *gnum;      // G*G: vectors of each cell
+    int32_t *gvec;      // K: vector ids by cell
+    double *gvh;        // K x 4: their unit directions, by cell
+    int32_t *lcnt;      // G*G: candidate-list length (-1: full scan)
+    int32_t *lstart;    // G*G: first record of each list (-1: full scan)
+    unsigned long long *gtot;  // 1: the allocator of the cells' vector ranges (build)
+    double *lrec;       // gcap x 4: (v, |v|) of the list entries
+    int32_t *lidx;      // gcap: vector id of each record
     int32_t *vs;        // K x 2: valid slots, ascending, each with its physical row
     int32_t *nvalid;    // 1
     int32_t *stamp;     // K+N: the generation that will read the row (rows of

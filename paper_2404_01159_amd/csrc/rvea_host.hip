@@ -22,17 +22,21 @@ namespace {
 constexpr int kKernels = 5;  // timed kernel ids: offspring, assoc, rerank, gamma, rollout
 constexpr int kLqFloats = 32 * 32 + 32 * 8 + kPolicyE * 32;  // A, B, x0 of the policy problem
 
-struct Layout {
-    int ld, stride, KC, CS, osplit;
-    size_t off[40];
-    size_t total;
-};
-
 enum Buf {
     B_X, B_SLOT, B_OFF, B_VALID, B_FM, B_MVALID, B_PARENTS, B_VS,
     B_NVALID, B_STAMP, B_V0, B_V, B_V32, B_VN, B_GAMMA, B_ZBITS, B_RBITS, B_PMAX, B_PMASK,
     B_ASSOC, B_APD, B_KEY, B_SURV, B_TDONE, B_COUNTERS, B_VCHANGED, B_BCOUNT, B_FREECNT, B_PEN,
-    B_NDONE, B_LQ, B_GPART, B_VEL, B_COUNT
+    B_NDONE, B_LQ, B_GPART, B_VEL,
+    B_GR, B_GCELL, B_GCNT, B_GSTART, B_GNUM, B_GVEC, B_GVH, B_LCNT, B_LSTART, B_GTOT,
+    B_LREC, B_LIDX, B_COUNT
+};
+
+struct Layout {
+    int ld, stride, KC, CS, osplit;
+    int gG;        // index grid side (0: none)
+    int64_t gcap;  // index list records
+    size_t off[B_COUNT];
+    size_t total;
 };
 
 int64_t binomial(int64_t n, int64_t k)
@@ -107,7 +111,13 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, int op, Layout
     L.KC = (int)((K + cs - 1) / cs);
     const int64_t P = (N + 1) / 2;
     L.osplit = op == OP_GA ? offspring_splits(d, N) : 1;
-    const size_t sz[B_COUNT] = {
+    // index of the vectors (three objectives): G x G cells, G = 1.4 sqrt(K)
+    // (about one cell inside the simplex per vector), each with a slot of
+    // grid_slot() list records (the lists average about five)
+    L.gG = grid_side(m, K);
+    const size_t cells = (size_t)L.gG * L.gG;
+    L.gcap = (int64_t)grid_slot() * (int64_t)cells;
+    const size_t sz[] = {
         (size_t)(K + N) * L.ld * 4, (size_t)2 * K * 4, (size_t)N * 4, (size_t)2 * K,
         (size_t)2 * M * m * 4, (size_t)M,
         (size_t)P * 2 * 4, (size_t)K * 8, 4, (size_t)(K + N) * 4, (size_t)K * m * 8,
@@ -117,7 +127,10 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, int op, Layout
         (size_t)((K + N + 255) / 256) * 4, 4, 8, 4,
         problem == kPolicy ? (size_t)kLqFloats * 4 : 0,
         L.osplit > 1 ? (size_t)P * L.osplit * 2 * 8 : 8,
-        swarm(op) ? (size_t)(K + N) * L.ld * 4 : 8};
+        swarm(op) ? (size_t)(K + N) * L.ld * 4 : 8,
+        (size_t)m * 8, (size_t)K * 4, cells * 4, cells * 4, cells * 4, (size_t)K * 4,
+        (size_t)K * 32, cells * 4, cells * 4, 16, (size_t)L.gcap * 32, (size_t)L.gcap * 4};
+    static_assert(sizeof(sz) / sizeof(sz[0]) == B_COUNT, "one size per buffer");
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -183,6 +196,9 @@ struct rvea_batch_s {
 };
 
 namespace {
+
+// the index's scaling before any adaptation (and after a host-set V)
+const double kUnitScale[3] = {1.0, 1.0, 1.0};
 
 // message of the last failed rvea_create on this thread (no handle exists)
 thread_local char g_create_err[512] = "";
@@ -419,6 +435,22 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     R.op_a = p.op_a;
     R.op_b = p.op_b;
     R.Vel = swarm(p.op) ? (float *)(w + L.off[B_VEL]) : nullptr;
+    R.gG = L.gG;
+    R.gcap = L.gcap;
+    if (L.gG > 0) {
+        R.gr = (double *)(w + L.off[B_GR]);
+        R.gcell = (int32_t *)(w + L.off[B_GCELL]);
+        R.gcnt = (int32_t *)(w + L.off[B_GCNT]);
+        R.gstart = (int32_t *)(w + L.off[B_GSTART]);
+        R.gnum = (int32_t *)(w + L.off[B_GNUM]);
+        R.gvec = (int32_t *)(w + L.off[B_GVEC]);
+        R.gvh = (double *)(w + L.off[B_GVH]);
+        R.lcnt = (int32_t *)(w + L.off[B_LCNT]);
+        R.lstart = (int32_t *)(w + L.off[B_LSTART]);
+        R.gtot = (unsigned long long *)(w + L.off[B_GTOT]);
+        R.lrec = (double *)(w + L.off[B_LREC]);
+        R.lidx = (int32_t *)(w + L.off[B_LIDX]);
+    }
     R.vs = (int32_t *)(w + L.off[B_VS]);
     R.nvalid = (int32_t *)(w + L.off[B_NVALID]);
     R.stamp = (int32_t *)(w + L.off[B_STAMP]);
@@ -469,8 +501,16 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     if (e == hipSuccess) e = hipMemsetAsync(R.ndone, 0, 4, r->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(R.stamp, 0xff, (size_t)(K + N) * 4, r->stream);
+    if (e == hipSuccess && R.gG > 0) {  // the index starts unscaled, with no vectors counted
+        e = hipMemcpyAsync(R.gr, kUnitScale, 3 * sizeof(double), hipMemcpyHostToDevice,
+                           r->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(R.gcnt, 0, (size_t)R.gG * R.gG * 4, r->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(R.gtot, 0, 16, r->stream);
+    }
     if (e == hipSuccess) e = launch_lattice(R, r->stream, r->H);
     if (e == hipSuccess) e = launch_gamma(R, r->stream, 1);
+    if (e == hipSuccess) e = launch_grid_build(R, r->stream, 1);
     if (e == hipSuccess) e = launch_init(R, r->stream);
     if (e != hipSuccess) {
         std::snprintf(g_create_err, sizeof g_create_err, "initialization: %s (%d)",
@@ -786,6 +826,11 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
         HIPCHK(r, hipMemcpy(R.gamma, gamma, (size_t)R.K * 8, hipMemcpyHostToDevice));
     else if (V)
         HIPCHK(r, launch_gamma(R, r->stream, 1));
+    if (V && r->L.gG > 0) {  // a host-set V: the index unscaled and rebuilt
+        HIPCHK(r, hipStreamSynchronize(r->stream));
+        HIPCHK(r, hipMemcpy(R.gr, kUnitScale, 3 * sizeof(double), hipMemcpyHostToDevice));
+        if (R.gG > 0) HIPCHK(r, launch_grid_build(R, r->stream, 1));
+    }
     HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));
     HIPCHK(r, hipMemset(R.stamp, 0xff, (size_t)(R.K + R.N) * 4));
     HIPCHK(r, hipMemset(R.zbits, 0xff, (size_t)2 * R.m * 4));
@@ -943,6 +988,21 @@ rvea_status rvea_set_graphs(rvea_run r, int enable)
     return RVEA_OK;
 }
 
+rvea_status rvea_set_index(rvea_run r, int enable)
+{
+    if (!r) return RVEA_EINVAL;
+    if (r->phase != 0 || r->batch) return RVEA_ESTATE;
+    if (enable && r->L.gG == 0) return RVEA_EUNSUPPORTED;
+    const int G = enable ? r->L.gG : 0;
+    if (G == r->R.gG) return RVEA_OK;
+    HIPCHK(r, hipStreamSynchronize(r->stream));
+    r->R.gG = G;
+    // V may have changed while the index was off
+    if (G > 0) HIPCHK(r, launch_grid_build(r->R, r->stream, 1));
+    drop_graphs(r);  // they hold the old launch sequence
+    return RVEA_OK;
+}
+
 rvea_status rvea_set_timing(rvea_run r, int kernel_mask)
 {
     if (!r) return RVEA_EINVAL;
@@ -1088,6 +1148,10 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     };
     int cus = 0;
     HIPCHK(r, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device));
+    // the full-scan passes' shapes are tuned with the index off (they serve
+    // the gamma pass, batches, and runs without an index)
+    const int gG0 = R.gG;
+    R.gG = 0;
     std::vector<Cand> cands;
     for (int rr : {4, 2, 1})
         for (int cs : chunk_candidates(R.M, R.K, rr, CS0, KC0, cus)) cands.push_back({rr, cs, 0.f});
@@ -1168,6 +1232,7 @@ rvea_status rvea_autotune(rvea_run r, rvea_tuning *out)
     R.grr = g_rr;
     R.gCS = g_cs;
     R.gKC = (int)((R.K + g_cs - 1) / g_cs);
+    R.gG = gG0;
     HIPCHK(r, hipMemcpy(R.counters, saved, sizeof saved, hipMemcpyHostToDevice));
     // the trial's preparation handed out free rows: the real one starts over
     HIPCHK(r, hipMemsetAsync(R.freecnt, 0, 4, r->stream));
@@ -1324,6 +1389,12 @@ rvea_status rvea_batch_retire(rvea_batch b, rvea_run r)
     b->runs.erase(std::find(b->runs.begin(), b->runs.end(), r));
     r->batch = nullptr;
     b->dirty = true;
+    // the batch adapted V through the full-scan passes: the run's index
+    // follows on its own stream
+    if (r->R.gG > 0) {
+        const hipError_t e = launch_grid_build(r->R, r->stream, 1);
+        if (e != hipSuccess) return bfail(b, e, "index rebuild");
+    }
     return RVEA_OK;
 }
 

@@ -39,6 +39,12 @@ hipError_t launch_stamp(const RunView &R, hipStream_t s);
 hipError_t launch_offspring(const RunView &R, hipStream_t s);
 hipError_t launch_operator(const RunView &R, hipStream_t s);  // DE, PSO, CSO, random
 hipError_t launch_assoc(const RunView &R, hipStream_t s);
+// indexed association (three objectives): the index of V, rebuilt when V
+// changes (force, or the adaptation's changed flag), and the association
+int grid_side(int m, int64_t K);  // cells per side (0: not indexed)
+int grid_slot();                  // list records per cell
+hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force);
+hipError_t launch_assoc_grid(const RunView &R, hipStream_t s);
 hipError_t launch_rerank(const RunView &R, hipStream_t s);
 hipError_t launch_select_back(const RunView &R, hipStream_t s);
 hipError_t launch_adapt(const RunView &R, hipStream_t s);

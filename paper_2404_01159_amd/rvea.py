@@ -27,7 +27,7 @@ EXPORTS = [
     "rvea_default_params", "rvea_lattice_divisions", "rvea_footprint", "rvea_create",
     "rvea_create_policy",
     "rvea_step", "rvea_select", "rvea_adapt", "rvea_run_generations",
-    "rvea_prepare_generations", "rvea_set_graphs",
+    "rvea_prepare_generations", "rvea_set_graphs", "rvea_set_index",
     "rvea_get_state",
     "rvea_set_state", "rvea_get_offspring", "rvea_get_selection", "rvea_get_rows",
     "rvea_operator_params", "rvea_get_velocities", "rvea_set_velocities",
@@ -92,6 +92,7 @@ def _load():
         "rvea_run_generations": [P, i32],
         "rvea_prepare_generations": [P, i32],
         "rvea_set_graphs": [P, i32],
+        "rvea_set_index": [P, i32],
         "rvea_get_state": [P, P, P, P, P, P, P, P],
         "rvea_set_state": [P, P, P, P, P, P, i64],
         "rvea_get_offspring": [P, P, P, P],
@@ -253,6 +254,11 @@ class Run:
 
     def set_graphs(self, on):
         self._chk(lib.rvea_set_graphs(self._h, 1 if on else 0), "rvea_set_graphs")
+
+    def set_index(self, on):
+        """Association through the vector index (True, the default for m = 3)
+        or by full scans (False); the results are the same."""
+        self._chk(lib.rvea_set_index(self._h, 1 if on else 0), "rvea_set_index")
 
     def synchronize(self):
         self._chk(lib.rvea_synchronize(self._h), "rvea_synchronize")

@@ -1,0 +1,125 @@
+"""The indexed association (three objectives) against the full scan through
+the C ABI: the same association, APD (bit for bit) and survivors every
+generation, adaptations included, at small shapes, at the 10,011-vector
+shape, after a host-set V whose index is unscaled, and after a run leaves a
+batch (its index rebuilt for the vectors the batch adapted).  Both paths are
+also checked against the oracle by the other GPU tests (the index is the
+default for m = 3)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2404_01159_amd as P
+
+    return P
+
+
+def same_selection(a, b, t):
+    sa, sb = a.get_selection(), b.get_selection()
+    for k in ("zstar", "assoc", "surv"):
+        assert np.array_equal(sa[k], sb[k]), f"{k} differs at t={t}"
+    assert np.array_equal(sa["apd"].view(np.uint64), sb["apd"].view(np.uint64)), \
+        f"apd differs at t={t}"
+
+
+def twin(P, problem, m, d, N, K, seed, t_max):
+    prm = P.default_params(t_max=t_max)
+    a = P.Run(problem, m, d, N, K, seed=seed, params=prm)
+    b = P.Run(problem, m, d, N, K, seed=seed, params=prm)
+    b.set_index(False)
+    return a, b
+
+
+def lock(a, b, gens):
+    for _ in range(gens):
+        a.step()
+        b.step()
+        a.select()
+        b.select()
+        same_selection(a, b, a.counters()["generations"])
+        a.adapt()
+        b.adapt()
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("X", "F", "valid", "V", "gamma"):
+        assert np.array_equal(sa[k], sb[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("case", [(1, 3, 30, 105, 105, 25, 30), (2, 3, 12, 40, 55, 25, 20),
+                                  (3, 3, 64, 300, 351, 21, 20), (1, 3, 10, 3, 3, 12, 10)],
+                         ids=lambda c: "p%d_d%d_N%d_K%d" % (c[0], c[2], c[3], c[4]))
+def test_index_matches_full_scan(P, case):
+    problem, m, d, N, K, gens, t_max = case
+    print(f"index vs scan {case}", flush=True)
+    a, b = twin(P, problem, m, d, N, K, 7, t_max)
+    lock(a, b, gens)
+    assert a.counters()["full_rescans"] == 0
+    a.close()
+    b.close()
+
+
+def test_index_matches_full_scan_headline(P):
+    print("index vs scan at 10,011 vectors", flush=True)
+    a, b = twin(P, 1, 3, 500, 10011, 10011, 3, 100)
+    lock(a, b, 12)  # one adaptation (generation 10)
+    assert a.counters()["full_rescans"] == 0
+    a.close()
+    b.close()
+
+
+def test_index_after_host_set_vectors(P):
+    # an adapted-looking V set from the host: the index is rebuilt unscaled
+    import oracle as O
+
+    a, b = twin(P, 2, 3, 20, 200, 231, 11, 40)
+    st = a.get_state()
+    V = O.unit_vectors(O.lattice_H(231, 3), 3) * np.array([30.0, 1.0, 0.2])
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = st["F"] * np.array([30.0, 1.0, 0.2], np.float32)
+    for r in (a, b):
+        r.set_state(st["X"], F, st["valid"], V=V, t=0)
+    lock(a, b, 9)
+    a.close()
+    b.close()
+
+
+def test_index_rebuilt_after_a_batch(P):
+    prm = P.default_params(t_max=20)
+    a = P.Run(1, 3, 40, 105, 105, seed=5, params=prm)
+    b = P.Run(1, 3, 40, 105, 105, seed=5, params=prm)
+    for _ in range(3):
+        a.generation()
+        b.generation()
+    bt = P.Batch(2)
+    bt.admit(a)
+    bt.step(8)  # adaptations at 4 and 8 in the batch
+    bt.retire(a)
+    bt.close()
+    for _ in range(8):
+        b.generation()
+    lock(a, b, 6)
+    a.close()
+    b.close()
+
+
+def test_index_switch_and_rejections(P):
+    a = P.Run(1, 3, 20, 105, 105, seed=1)
+    a.set_index(False)
+    a.set_index(True)
+    a.generation()
+    p2 = P.Run(1, 2, 20, 10, 10, seed=1)
+    with pytest.raises(P.RveaError):
+        p2.set_index(True)
+    p2.set_index(False)
+    a.step()
+    with pytest.raises(P.RveaError):
+        a.set_index(False)  # between step and select
+    a.close()
+    p2.close()
