@@ -52,6 +52,11 @@ def kernel_work(name, run):
             return "bytes", 2 * P * d * 4 + N * d * 4 + N * m * 4
         reads, writes = operator_rows(op, N, K)
         return "bytes", (reads + writes) * d * 4 + N * m * 4
+    if name == "assoc" and getattr(run, "indexed", False):
+        # indexed association: per merged row its objectives and take-part
+        # flag read, association and APD written, one 8-byte atomic minimum
+        # (the candidate lists, about five records per row, stay in cache)
+        return "bytes", (K + N) * (4 * m + 1 + 4 + 8 + 8)
     if name == "assoc":
         # every (merged row, vector) pair: an m-term dot product (m fused
         # multiply-adds, 2m flops) and one max
@@ -109,8 +114,9 @@ def sweeps_leg(a):
                         K=c["K"], ms_per_generation=el * 1e3 / c["gens"],
                         generations_per_s=c["gens"] / el,
                         offspring_us=off["avg_launch_us"], offspring_hbm_frac=off["frac"],
-                        assoc_us=asc["avg_launch_us"], assoc_fp32_frac=asc["frac"],
-                        rerank_us=t["rerank"] * 1e3))
+                        assoc_us=asc["avg_launch_us"], assoc_bound=asc["bound"],
+                        assoc_frac=asc["frac"],
+                        rerank_us=None if run.indexed else t["rerank"] * 1e3))
     return dict(workload="Series 1: m=3, d=100, n=2^5..2^14; Series 2: m=3, n=100, "
                          "d=2^9..2^18; N=n, K=the smallest lattice count >= n, 100 generations",
                 points=pts)
@@ -502,6 +508,24 @@ def main():
     # launched REPS times back to back between two HIP events on the run's
     # stream (a replayed graph cannot carry fresh events, and an event pair
     # around every single launch adds its own dispatch time)
+    # the same generations with the association by full scans (identical
+    # results): what the vector index gains on this workload
+    full_scan = None
+    if run.indexed and not a.no_timing:
+        fs = P.Run(cfg["problem"], cfg["m"], cfg["d"], cfg["N"], cfg["K"], seed=cfg["seed"],
+                   params=prm, device="cuda:0")
+        fs.set_index(False)
+        if not a.no_autotune:
+            fs.autotune()
+        fs.prepare(a.steps)
+        fs.synchronize()
+        t0 = time.perf_counter()
+        fs.run(a.steps)
+        fs.synchronize()
+        fel = time.perf_counter() - t0
+        fs.close()
+        full_scan = dict(generations_per_s=a.steps / fel, ms_per_generation=fel * 1e3 / a.steps)
+
     roof = None
     rooflines = {}
     per_kernel = {}
@@ -511,7 +535,8 @@ def main():
         run.select()
         run.adapt()
         run.synchronize()
-        for k in ("offspring", "assoc", "rerank"):
+        # the indexed association has no separate re-rank
+        for k in ("offspring", "assoc") + (() if run.indexed else ("rerank",)):
             per_kernel[k] = (t[k], TIMING_REPS)
         dom = max(per_kernel, key=lambda k: per_kernel[k][0])
         for k in ("offspring", "assoc"):
@@ -565,6 +590,7 @@ def main():
         "rooflines": rooflines,
         "kernels_avg_us": {k: v[0] * 1e3 for k, v in per_kernel.items()},
         "assoc_tiles": tuning,
+        "association_by_full_scan": full_scan,
         "counters": counters,
         "cpu_baseline": cpu,
         "serving": serving,

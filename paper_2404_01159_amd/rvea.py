@@ -189,6 +189,7 @@ class Run:
         self.problem, self.m, self.d, self.N, self.K = problem, m, d, N, K
         self.M = K + N
         self.seed = seed
+        self.indexed = m == 3  # the library's default association
         self.params = params if params is not None else default_params()
         self.bytes = footprint(problem, m, d, N, K, self.params)
         dev = torch.device(device)
@@ -259,6 +260,7 @@ class Run:
         """Association through the vector index (True, the default for m = 3)
         or by full scans (False); the results are the same."""
         self._chk(lib.rvea_set_index(self._h, 1 if on else 0), "rvea_set_index")
+        self.indexed = bool(on)
 
     def synchronize(self):
         self._chk(lib.rvea_synchronize(self._h), "rvea_synchronize")
