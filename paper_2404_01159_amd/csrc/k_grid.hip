@@ -306,6 +306,7 @@ __global__ __launch_bounds__(256) void k_grid_bucket(RunView R, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j == 0) R.gtot[1] = 0;  // the full gamma pass not needed (yet)
     if (j >= R.K) return;
     int c = cell_of(R.V[j * 3], R.V[j * 3 + 1], R.V[j * 3 + 2], R.gr, R.gG);
     if (c < 0) c = 0;  // cannot happen for a nonzero vector >= 0
@@ -387,6 +388,45 @@ struct Stage {
     int n;
 };
 
+// least distance from unit u to the boundary of the box of cells of radius
+// k around (ci, cj), clipped to the simplex (sides on the grid's edge, where
+// the simplex ends, do not count): the sides are exact grid lines in
+// binary64 (their ends on the simplex's edge), lifted in binary32, so the
+// callers compare it with their slack
+__device__ float box_side_min(const RunView &R, int ci, int cj, int k, const F3 &u)
+{
+    const int G = R.gG;
+    const int i0 = max(0, ci - k), i1 = min(G - 1, ci + k);
+    const int j0 = max(0, cj - k), j1 = min(G - 1, cj + k);
+    const double h = 1.0 / G;
+    float lo = INFINITY;
+    if (i0 > 0) {
+        const double x = i0 * h, ya = j0 * h, yb = fmin((j1 + 1) * h, 1.0 - x);
+        if (yb >= ya)
+            lo = fminf(lo, farc_chord_of(u, flift((float)x, (float)ya, R.gr),
+                                         flift((float)x, (float)yb, R.gr)));
+    }
+    if (i1 < G - 1) {
+        const double x = (i1 + 1) * h, ya = j0 * h, yb = fmin((j1 + 1) * h, 1.0 - x);
+        if (yb >= ya)
+            lo = fminf(lo, farc_chord_of(u, flift((float)x, (float)ya, R.gr),
+                                         flift((float)x, (float)yb, R.gr)));
+    }
+    if (j0 > 0) {
+        const double y = j0 * h, xa = i0 * h, xb = fmin((i1 + 1) * h, 1.0 - y);
+        if (xb >= xa)
+            lo = fminf(lo, farc_chord_of(u, flift((float)xa, (float)y, R.gr),
+                                         flift((float)xb, (float)y, R.gr)));
+    }
+    if (j1 < G - 1) {
+        const double y = (j1 + 1) * h, xa = i0 * h, xb = fmin((i1 + 1) * h, 1.0 - y);
+        if (xb >= xa)
+            lo = fminf(lo, farc_chord_of(u, flift((float)xa, (float)y, R.gr),
+                                         flift((float)xb, (float)y, R.gr)));
+    }
+    return lo;
+}
+
 // One wavefront per cell: the neighbourhood staged in LDS; b from the
 // cells within kNear; the box radius (lane k tests radius k, at most
 // kStage); the champions and the list from the staged box vectors, written
@@ -458,6 +498,46 @@ __global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
         }
     }
     __syncthreads();
+    // Eq. 5's gamma of the cell's own vectors: the largest binary64 cosine
+    // to another vector that is not parallel to it (cosine below 1, as the
+    // full pass computes it), kept when the staged neighbourhood provably
+    // holds that vector (the nearest staged one is closer than the
+    // neighbourhood's boundary); otherwise the full gamma pass is asked for
+    {
+        const int own = kStage * kStageW + kStage;  // the centre cell's lane
+        const int oq0 = __builtin_amdgcn_readlane(incl0 - mine0, own);
+        const int on = full ? 0 : __builtin_amdgcn_readlane(cnt[0], own);
+        bool need = full && __builtin_amdgcn_readlane(cnt[0], own) > 0;
+        for (int o = oq0; o < oq0 + on; ++o) {  // uniform
+            const int32_t id = st.j[o];
+            const double vi[3] = {st.rec[o][0], st.rec[o][1], st.rec[o][2]};
+            const double vni = st.rec[o][3];
+            const F3 ui = f3(st.vh[o][0], st.vh[o][1], st.vh[o][2]);
+            double gb = -INFINITY;
+            float dmin = INFINITY;
+            for (int q = lane; q < nst; q += 64) {
+                if (st.j[q] == id) continue;
+                double sd = vi[0] * st.rec[q][0];
+                sd = fma(vi[1], st.rec[q][1], sd);
+                sd = fma(vi[2], st.rec[q][2], sd);
+                const double cv = sd / (vni * st.rec[q][3]);
+                if (cv >= 1.0) continue;
+                gb = fmax(gb, cv);
+                dmin = fminf(dmin, fchord(ui, f3(st.vh[q][0], st.vh[q][1], st.vh[q][2])));
+            }
+            gb = -wave_fmin(-gb);
+            dmin = (float)wave_fmin((double)dmin);
+            float lo = 0.0f;
+            if (lane == 0) lo = box_side_min(R, ci, cj, kStage, ui);
+            lo = __shfl(lo, 0, 64);
+            if (dmin < INFINITY && lo > dmin + 2.0f * kSlack) {
+                if (lane == 0) R.gamma[id] = acos(gb < -1.0 ? -1.0 : gb);
+            } else {
+                need = true;
+            }
+        }
+        if (need && lane == 0) R.gtot[1] = 1;
+    }
     // b: the best covering vector among the cells within kNear
     float best = INFINITY;
     if (!full) {
@@ -475,42 +555,8 @@ __global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
     int kc = 0x7fffffff;
     if (!full) {  // lane k: does the box of radius k hold the ball of radius b + rho?
         const int k = lane;
-        bool ok = false;
-        if (k <= kStage) {
-            const int i0 = max(0, ci - k), i1 = min(G - 1, ci + k);
-            const int j0 = max(0, cj - k), j1 = min(G - 1, cj + k);
-            // the sides are exact grid lines in binary64 (their ends on the
-            // simplex's edge), lifted in binary32; the slack covers both
-            const double h = 1.0 / G;
-            const float rad = b + g.rho + 2.0f * kSlack;
-            const F3 ucf = ld3(g.ucf);
-            float lo = INFINITY;
-            if (i0 > 0) {
-                const double x = i0 * h, ya = j0 * h, yb = fmin((j1 + 1) * h, 1.0 - x);
-                if (yb >= ya)
-                    lo = fminf(lo, farc_chord_of(ucf, flift((float)x, (float)ya, R.gr),
-                                                 flift((float)x, (float)yb, R.gr)));
-            }
-            if (i1 < G - 1) {
-                const double x = (i1 + 1) * h, ya = j0 * h, yb = fmin((j1 + 1) * h, 1.0 - x);
-                if (yb >= ya)
-                    lo = fminf(lo, farc_chord_of(ucf, flift((float)x, (float)ya, R.gr),
-                                                 flift((float)x, (float)yb, R.gr)));
-            }
-            if (j0 > 0) {
-                const double y = j0 * h, xa = i0 * h, xb = fmin((i1 + 1) * h, 1.0 - y);
-                if (xb >= xa)
-                    lo = fminf(lo, farc_chord_of(ucf, flift((float)xa, (float)y, R.gr),
-                                                 flift((float)xb, (float)y, R.gr)));
-            }
-            if (j1 < G - 1) {
-                const double y = (j1 + 1) * h, xa = i0 * h, xb = fmin((i1 + 1) * h, 1.0 - y);
-                if (xb >= xa)
-                    lo = fminf(lo, farc_chord_of(ucf, flift((float)xa, (float)y, R.gr),
-                                                 flift((float)xb, (float)y, R.gr)));
-            }
-            ok = lo > rad;
-        }
+        const bool ok =
+            k <= kStage && box_side_min(R, ci, cj, k, ld3(g.ucf)) > b + g.rho + 2.0f * kSlack;
         kc = wave_imin(ok ? k : 0x7fffffff);
         full = kc == 0x7fffffff;
     }

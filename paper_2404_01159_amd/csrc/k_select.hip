@@ -82,7 +82,9 @@ __device__ __forceinline__ float dotf(const float *f, const float4 *v)
 template <int MD, int RR, bool GAMMA>
 __device__ __forceinline__ void assoc_body(const RunView &R, int64_t bx, int c, int gate)
 {
-    if (GAMMA && !gate && *R.vchanged == 0) return;  // uniform: vectors unchanged
+    // gamma pass, uniform exits: gate 1 always runs; gate 0 runs when the
+    // vectors changed; gate 2 also needs the index to have asked for it
+    if (GAMMA && gate != 1 && (*R.vchanged == 0 || (gate == 2 && R.gtot[1] == 0))) return;
     constexpr int NV4 = MD <= 4 ? 1 : 2;  // float4 per vector
     __shared__ float4 sv[1024 * NV4];
     const int64_t j0 = (int64_t)c * R.CS;
@@ -252,7 +254,9 @@ __device__ __forceinline__ void rerank_body(const RunView &R, int64_t bx, int ga
 {
     constexpr int kLanes = 64 / kRows;  // lanes per row in phase 1
     constexpr int kWaveItems = 12 * kRows < kItems ? kItems : 12 * kRows;  // tiles per wave
-    if (GAMMA && !gate && *R.vchanged == 0) return;  // uniform: vectors unchanged
+    // gamma pass, uniform exits: gate 1 always runs; gate 0 runs when the
+    // vectors changed; gate 2 also needs the index to have asked for it
+    if (GAMMA && gate != 1 && (*R.vchanged == 0 || (gate == 2 && R.gtot[1] == 0))) return;
     __shared__ double s_f[kRows][MD];
     __shared__ double s_nrm[kRows];
     __shared__ int s_state[kRows];  // 0 inactive, 1 items, 2 zero row, 3 full scan

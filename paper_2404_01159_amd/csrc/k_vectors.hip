@@ -200,9 +200,15 @@ hipError_t launch_adapt(const RunView &R, hipStream_t s)
     k_adapt_v<<<blocks(R.K, 256), 256, 0, s>>>(R);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_gamma(R, s, 0);
-    if (e != hipSuccess) return e;
-    return launch_grid_build(R, s, 0);
+    // with the index, its build computes gamma where it can prove the nearest
+    // vector is among a vector's neighbours, and the full pass runs only when
+    // some vector is left
+    if (R.gG > 0) {
+        e = launch_grid_build(R, s, 0);
+        if (e != hipSuccess) return e;
+        return launch_gamma(R, s, 2);
+    }
+    return launch_gamma(R, s, 0);
 }
 
 }  // namespace rvea

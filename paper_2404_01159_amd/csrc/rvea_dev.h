@@ -70,7 +70,8 @@ struct RunView {
     double *gvh;        // K x 4: their unit directions, by cell
     int32_t *lcnt;      // G*G: candidate-list length (-1: full scan)
     int32_t *lstart;    // G*G: first record of each list (-1: full scan)
-    unsigned long long *gtot;  // 1: the allocator of the cells' vector ranges (build)
+    unsigned long long *gtot;  // 2: the allocator of the cells' vector ranges (build),
+                               // and 1 when the build left some vector's gamma
     double *lrec;       // gcap x 4: (v, |v|) of the list entries
     int32_t *lidx;      // gcap: vector id of each record
     int32_t *vs;        // K x 2: valid slots, ascending, each with its physical row
