@@ -344,32 +344,63 @@ __global__ __launch_bounds__(256) void k_grid_fill(RunView R, int gate)
         make_double4(R.V[j * 3] * inv, R.V[j * 3 + 1] * inv, R.V[j * 3 + 2] * inv, 0.0);
 }
 
-// wavefront-wide minimum / sum / best (largest value, lowest id on ties)
-// over the 64 lanes (every lane active)
+// Wavefront-wide minimum / best (largest value, lowest id on ties) over
+// the 64 lanes (every lane active): the pairings of partner32 within each
+// half, then the two halves' results read out and combined (the result is
+// uniform).
 __device__ __forceinline__ double wave_fmin(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmin(v, partner32<0>(v));
+    v = fmin(v, partner32<1>(v));
+    v = fmin(v, partner32<2>(v));
+    v = fmin(v, partner32<3>(v));
+    v = fmin(v, partner32<4>(v));
+    RVEA_ASSERT_FULL_WAVE();
+    const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                      __builtin_amdgcn_readlane(__double2loint(v), 0));
+    const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                      __builtin_amdgcn_readlane(__double2loint(v), 32));
+    return fmin(a, b);
 }
 __device__ __forceinline__ int wave_imin(int v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
+    v = min(v, partner32<0>(v));
+    v = min(v, partner32<1>(v));
+    v = min(v, partner32<2>(v));
+    v = min(v, partner32<3>(v));
+    v = min(v, partner32<4>(v));
+    RVEA_ASSERT_FULL_WAVE();
+    return min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 32));
+}
+template <int L>
+__device__ __forceinline__ void best_step(double &v, int32_t &j, int32_t &p)
+{
+    const double ov = partner32<L>(v);
+    const int32_t oj = partner32<L>((int)j), op = partner32<L>((int)p);
+    if (ov > v || (ov == v && oj < j)) {
+        v = ov;
+        j = oj;
+        p = op;
+    }
 }
 __device__ __forceinline__ void wave_best(double &v, int32_t &j, int32_t &p)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(v, o, 64);
-        const int32_t oj = __shfl_xor(j, o, 64), op = __shfl_xor(p, o, 64);
-        if (ov > v || (ov == v && oj < j)) {
-            v = ov;
-            j = oj;
-            p = op;
-        }
-    }
+    best_step<0>(v, j, p);
+    best_step<1>(v, j, p);
+    best_step<2>(v, j, p);
+    best_step<3>(v, j, p);
+    best_step<4>(v, j, p);
+    RVEA_ASSERT_FULL_WAVE();
+    const double v0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 0));
+    const double v1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 32));
+    const int32_t j0 = __builtin_amdgcn_readlane(j, 0), j1 = __builtin_amdgcn_readlane(j, 32);
+    const int32_t p0 = __builtin_amdgcn_readlane(p, 0), p1 = __builtin_amdgcn_readlane(p, 32);
+    const bool second = v1 > v0 || (v1 == v0 && j1 < j0);
+    v = second ? v1 : v0;
+    j = second ? j1 : j0;
+    p = second ? p1 : p0;
 }
 
 constexpr int kNear = 3;  // the covering search looks at the (2 kNear + 1)^2 cells around
@@ -529,7 +560,7 @@ __global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
             dmin = (float)wave_fmin((double)dmin);
             float lo = 0.0f;
             if (lane == 0) lo = box_side_min(R, ci, cj, kStage, ui);
-            lo = __shfl(lo, 0, 64);
+            lo = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lo)));
             if (dmin < INFINITY && lo > dmin + 2.0f * kSlack) {
                 if (lane == 0) R.gamma[id] = acos(gb < -1.0 ? -1.0 : gb);
             } else {
@@ -703,11 +734,18 @@ __global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
             }
         }
     }
-    // the row's lanes are adjacent: combine them (every lane active)
-#pragma unroll
-    for (int o = 1; o < kGridRowLanes; o <<= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int64_t oj = __shfl_xor(bj, o, 64);
+    // the row's four lanes are a quad: combine them by the quad swaps of
+    // partner32 (every lane active)
+    static_assert(kGridRowLanes == 4, "rows are quads");
+    {
+        double ob = partner32<0>(best);
+        int64_t oj = partner32<0>(bj);
+        if (ob > best || (ob == best && oj < bj)) {
+            best = ob;
+            bj = oj;
+        }
+        ob = partner32<1>(best);
+        oj = partner32<1>(bj);
         if (ob > best || (ob == best && oj < bj)) {
             best = ob;
             bj = oj;
@@ -762,7 +800,7 @@ int grid_slot() { return kSlot; }
 int grid_side(int m, int64_t K)
 {
     if (m != 3) return 0;
-    int G = (int)ceil(1.4 * sqrt((double)K));
+    int G = (int)ceil(1.0 * sqrt((double)K));
     return G < 2 ? 2 : G;
 }
 

@@ -111,9 +111,9 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, int op, Layout
     L.KC = (int)((K + cs - 1) / cs);
     const int64_t P = (N + 1) / 2;
     L.osplit = op == OP_GA ? offspring_splits(d, N) : 1;
-    // index of the vectors (three objectives): G x G cells, G = 1.4 sqrt(K)
-    // (about one cell inside the simplex per vector), each with a slot of
-    // grid_slot() list records (the lists average about five)
+    // index of the vectors (three objectives): G x G cells, G = sqrt(K)
+    // (about two vectors per cell inside the simplex), each with a slot of
+    // grid_slot() list records (the lists average about eight)
     L.gG = grid_side(m, K);
     const size_t cells = (size_t)L.gG * L.gG;
     L.gcap = (int64_t)grid_slot() * (int64_t)cells;

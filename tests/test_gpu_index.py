@@ -123,3 +123,31 @@ def test_index_switch_and_rejections(P):
         a.set_index(False)  # between step and select
     a.close()
     p2.close()
+
+
+def test_index_crowded_vectors_fall_back_to_full_scans(P):
+    """Vectors crowded far below the grid's resolution (axis ranges
+    1 : 1e-3 : 1e-3 set from the host, so the index is unscaled): the crowded
+    cells' lists overflow or their boxes pass the staged neighbourhood, their
+    rows take the exact full scan (counted), gamma falls back to the full
+    pass, and every generation still equals the full-scan run; one generation
+    is also checked against the oracle."""
+    import oracle as O
+    from parity import lockstep, new_stats
+
+    a, b = twin(P, 2, 3, 12, 300, 351, 5, 50)
+    st = a.get_state()
+    scale = np.array([1.0, 1e-3, 1e-3])
+    V = O.unit_vectors(O.lattice_H(351, 3), 3) * scale
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = st["F"] * scale.astype(np.float32)
+    for r in (a, b):
+        r.set_state(st["X"], F, st["valid"], V=V, t=2)
+    assert np.array_equal(a.get_state()["gamma"], b.get_state()["gamma"])
+    lock(a, b, 3)
+    assert a.counters()["full_rescans"] > 0
+    prm = P.default_params(t_max=50)
+    stats = lockstep(O, a, prm, 1, new_stats())
+    assert stats["near_ties"] <= max(1, 1e-4 * stats["vectors"]), stats
+    a.close()
+    b.close()
