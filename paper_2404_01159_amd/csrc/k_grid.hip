@@ -706,13 +706,16 @@ __global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
         }
     }
     const bool full = live && (st < 0 || n <= 0);
-    double best = -INFINITY;
+    // the best cosine, its vector and that vector's gamma (loaded with the
+    // candidate, so the APD needs no further round trip)
+    double best = -INFINITY, bg = 0.0;
     int64_t bj = R.K;
     if (live && !full) {
         const double4 *rec = reinterpret_cast<const double4 *>(R.lrec) + st;
         for (int e = sub; e < n; e += kGridRowLanes) {
             const double4 v = rec[e];
             const int64_t j = R.lidx[st + e];
+            const double gj = R.gamma[j];
             double s = f[0] * v.x;
             s = fma(f[1], v.y, s);
             s = fma(f[2], v.z, s);
@@ -720,6 +723,7 @@ __global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
             if (cv > best || (cv == best && j < bj)) {
                 best = cv;
                 bj = j;
+                bg = gj;
             }
         }
     } else if (full) {
@@ -731,6 +735,7 @@ __global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
             if (cv > best || (cv == best && j < bj)) {
                 best = cv;
                 bj = j;
+                bg = R.gamma[j];
             }
         }
     }
@@ -738,17 +743,20 @@ __global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
     // partner32 (every lane active)
     static_assert(kGridRowLanes == 4, "rows are quads");
     {
-        double ob = partner32<0>(best);
+        double ob = partner32<0>(best), og = partner32<0>(bg);
         int64_t oj = partner32<0>(bj);
         if (ob > best || (ob == best && oj < bj)) {
             best = ob;
             bj = oj;
+            bg = og;
         }
         ob = partner32<1>(best);
+        og = partner32<1>(bg);
         oj = partner32<1>(bj);
         if (ob > best || (ob == best && oj < bj)) {
             best = ob;
             bj = oj;
+            bg = og;
         }
     }
     if (!in || sub != 0) return;
@@ -764,7 +772,7 @@ __global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
         return;
     }
     if (full) atomicAdd(&R.counters[1], 1ull);
-    const double gj = bj < R.K ? R.gamma[bj] : R.gamma[0];
+    const double gj = bj < R.K ? bg : R.gamma[0];
     if (bj >= R.K) bj = 0;
     const double cc = best > 1.0 ? 1.0 : (best < -1.0 ? -1.0 : best);
     const double th = acos(cc);
