@@ -38,7 +38,11 @@
 //          a margin far above binary64 rounding
 // Lists longer than kSlot, cells whose box would pass kStage cells from
 // C, and cells with no vector within kNear cells are marked for a full scan
-// (correct for any vector set, counted as full rescans).  Each cell's list
+// (correct for any vector set, counted as full rescans).  The same pass
+// gives Eq. 5's gamma of each vector whose nearest other vector provably lies
+// in its cell's staged neighbourhood (the nearest staged one is closer than
+// the neighbourhood's boundary); if any vector is left, it asks for the full
+// gamma pass.  Each cell's list
 // has a slot of kSlot records of its own; the cells' ranges of vector
 // positions are allocated by one atomic add per wavefront, so the order of
 // the vectors in memory varies from build to build (no result depends on it).
