@@ -754,18 +754,24 @@ int pick_segment(int d)
 }
 
 // The offspring kernel runs 4 wavefronts per SIMD (its register use), so
-// 256 CUs hold 4,096 at once.  With one pair per 64-lane segment, 4,097 to
-// 8,192 pairs would need a second, mostly idle round of wavefronts; 32-lane
-// segments (two pairs per wavefront, twice the quads per lane) fit them in
-// one.  A fixed constant, not the device's count, so that results (the
-// order of the distance sums) do not depend on the device.
+// 256 CUs hold 4,096 at once.  Rows of 256 genes or more take 32-lane
+// segments (two pairs per wavefront, twice the quads per lane) instead of
+// 64-lane ones when there are more pairs than resident wavefronts, and,
+// for rows under 2,048 genes, already above a quarter of that: a pair's own
+// work (mating, mutation sites, objectives) is then shared by the two
+// pairs of a wavefront, which outweighs having fewer wavefronts; long rows
+// with few pairs keep one pair per wavefront for the wavefront count.  A
+// fixed constant, not the device's count, so that results (the order of the
+// distance sums) do not depend on the device or on whether the run is
+// batched.
 constexpr int64_t kResidentOffspringWaves = 4096;
 
 int offspring_segment(int d, int64_t N)
 {
     const int S = pick_segment(d);
     const int64_t P = (N + 1) / 2;
-    if (S == 64 && P > kResidentOffspringWaves && P <= 2 * kResidentOffspringWaves) return 32;
+    if (S == 64 && (P > kResidentOffspringWaves || (P > kResidentOffspringWaves / 4 && d < 2048)))
+        return 32;
     return S;
 }
 
