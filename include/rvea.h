@@ -341,7 +341,8 @@ rvea_status rvea_destroy(rvea_run run);
  * A batch advances many independent runs (any problem, m, d, N, K) one
  * generation per rvea_batch_step: each phase of the generation is one launch
  * covering every admitted run (runs grouped by segment width or objective
- * count), and the launch sequence is captured into one HIP graph that is
+ * count; runs with the index of rvea_set_index associate through it and keep
+ * it rebuilt in phases of their own), and the launch sequence is captured into one HIP graph that is
  * replayed until the membership changes.  Each run keeps its own workspace,
  * state and Philox stream, so a run's results do not depend on what else is
  * in the batch.  Adaptation is decided on the device per run.

@@ -306,10 +306,10 @@ __device__ __forceinline__ int64_t wave_alloc(int n, unsigned long long *total)
 
 // ------------------------------------------------------------- build
 // vectors per cell (counts start at zero: the last build cleared them)
-__global__ __launch_bounds__(256) void k_grid_bucket(RunView R, int gate)
+__device__ __forceinline__ void grid_bucket_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     if (j == 0) R.gtot[1] = 0;  // the full gamma pass not needed (yet)
     if (j >= R.K) return;
     int c = cell_of(R.V[j * 3], R.V[j * 3 + 1], R.V[j * 3 + 2], R.gr, R.gG);
@@ -320,10 +320,10 @@ __global__ __launch_bounds__(256) void k_grid_bucket(RunView R, int gate)
 
 // each cell's range of positions (one atomic add per wavefront); the
 // counts become the fill cursors
-__global__ __launch_bounds__(256) void k_grid_ranges(RunView R, int gate)
+__device__ __forceinline__ void grid_ranges_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = bx * 256 + threadIdx.x;
     const int64_t cells = (int64_t)R.gG * R.gG;
     const int n = c < cells ? R.gcnt[c] : 0;
     const int64_t st = wave_alloc(n, &R.gtot[0]);
@@ -335,10 +335,10 @@ __global__ __launch_bounds__(256) void k_grid_ranges(RunView R, int gate)
 }
 
 // vectors into their cells' ranges, with their unit directions
-__global__ __launch_bounds__(256) void k_grid_fill(RunView R, int gate)
+__device__ __forceinline__ void grid_fill_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     if (j >= R.K) return;
     const int c = R.gcell[j];
     const int64_t p = R.gstart[c] + atomicAdd(&R.gcnt[c], 1);
@@ -469,11 +469,11 @@ __device__ float box_side_min(const RunView &R, int ci, int cj, int k, const F3 
 // A neighbourhood over kStageCap vectors or a box over kStage marks the cell
 // for a full scan.  Also clears the cell's fill cursor and the range
 // allocator for the next build.
-__global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
+__device__ __forceinline__ void grid_cells_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
     const int G = R.gG;
-    const int c = blockIdx.x;
+    const int c = (int)bx;
     const int lane = threadIdx.x;
     if (c >= G * G) return;  // uniform
     __shared__ CellGeo g;
@@ -679,10 +679,10 @@ __global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
 // cell's list (or of every vector for a cell marked for a full scan), the
 // best with the lowest index on ties, then as the re-rank: angle, APD of
 // Eq. 4 and the per-vector minimum of (APD, row).
-__global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
+__device__ __forceinline__ void assoc_grid_body(const RunView &R, int64_t bx)
 {
     const int sub = threadIdx.x % kGridRowLanes;
-    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kGridRowLanes;
+    const int64_t i = (bx * 256 + threadIdx.x) / kGridRowLanes;
     const bool in = i < R.M;
     const int64_t pop = *R.t_done;
     const uint32_t *zb = zbuf(R, pop + 1);
@@ -787,6 +787,53 @@ __global__ __launch_bounds__(256) void k_assoc_grid(RunView R)
     atomicMin(&R.key[bj], ((ab >> R.kb) << R.kb) | (unsigned long long)i);
 }
 
+// ------------------------------------------------------------- kernels
+__global__ __launch_bounds__(256) void k_grid_bucket(RunView R, int gate)
+{
+    grid_bucket_body(R, blockIdx.x, gate);
+}
+__global__ __launch_bounds__(256) void k_grid_ranges(RunView R, int gate)
+{
+    grid_ranges_body(R, blockIdx.x, gate);
+}
+__global__ __launch_bounds__(256) void k_grid_fill(RunView R, int gate)
+{
+    grid_fill_body(R, blockIdx.x, gate);
+}
+__global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
+{
+    grid_cells_body(R, blockIdx.x, gate);
+}
+__global__ __launch_bounds__(256) void k_assoc_grid(RunView R) { assoc_grid_body(R, blockIdx.x); }
+
+// batched: blockIdx.x decoded into (run, local block) through the span
+// table; the build phases run for the runs whose vectors changed
+__global__ __launch_bounds__(256) void kb_grid_bucket(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    grid_bucket_body(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+}
+__global__ __launch_bounds__(256) void kb_grid_ranges(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    grid_ranges_body(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+}
+__global__ __launch_bounds__(256) void kb_grid_fill(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    grid_fill_body(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+}
+__global__ __launch_bounds__(64) void kb_grid_cells(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    grid_cells_body(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+}
+__global__ __launch_bounds__(256) void kb_assoc_grid(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    assoc_grid_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+
 // ------------------------------------------------------------- launchers
 hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force)
 {
@@ -805,6 +852,35 @@ hipError_t launch_assoc_grid(const RunView &R, hipStream_t s)
     const int64_t threads = R.M * kGridRowLanes;
     k_assoc_grid<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(R);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_grid(int phase, const RunView *runs, const Span *sp, int n,
+                             int64_t blocks, hipStream_t s)
+{
+    const dim3 g((unsigned)blocks);
+    switch (phase) {
+    case BP_ASSOC: kb_assoc_grid<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_GRID_BUCKET: kb_grid_bucket<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_GRID_RANGES: kb_grid_ranges<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_GRID_FILL: kb_grid_fill<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_GRID_CELLS: kb_grid_cells<<<g, 64, 0, s>>>(runs, sp, n); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int64_t grid_phase_blocks(int phase, const RunView &R)
+{
+    if (R.gG <= 0) return 0;
+    const int64_t cells = (int64_t)R.gG * R.gG;
+    switch (phase) {
+    case BP_ASSOC: return (R.M * kGridRowLanes + 255) / 256;
+    case BP_GRID_BUCKET:
+    case BP_GRID_FILL: return (R.K + 255) / 256;
+    case BP_GRID_RANGES: return (cells + 255) / 256;
+    case BP_GRID_CELLS: return cells;
+    }
+    return 0;
 }
 
 int grid_slot() { return kSlot; }

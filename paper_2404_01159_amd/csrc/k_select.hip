@@ -779,13 +779,16 @@ __global__ __launch_bounds__(256) void kb_assoc(const RunView *runs, const Span 
     const int s = find_span(sp, n, blockIdx.x);
     const int64_t local = blockIdx.x - sp[s].start;
     const int64_t nbx = sp[s].nbx;
-    assoc_body<MD, RR, GAMMA>(runs[sp[s].run], local % nbx, (int)(local / nbx), 0);
+    const RunView &R = runs[sp[s].run];
+    // an indexed run's gamma pass also needs its index build to have asked
+    assoc_body<MD, RR, GAMMA>(R, local % nbx, (int)(local / nbx), R.gG > 0 ? 2 : 0);
 }
 template <int MD, bool GAMMA>
 __global__ __launch_bounds__(64) void kb_rerank(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
-    rerank_body<MD, GAMMA, kBatchRows>(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+    const RunView &R = runs[sp[s].run];
+    rerank_body<MD, GAMMA, kBatchRows>(R, blockIdx.x - sp[s].start, R.gG > 0 ? 2 : 0);
 }
 __global__ __launch_bounds__(256) void kb_newpop(const RunView *runs, const Span *sp, int n)
 {

@@ -1389,12 +1389,6 @@ rvea_status rvea_batch_retire(rvea_batch b, rvea_run r)
     b->runs.erase(std::find(b->runs.begin(), b->runs.end(), r));
     r->batch = nullptr;
     b->dirty = true;
-    // the batch adapted V through the full-scan passes: the run's index
-    // follows on its own stream
-    if (r->R.gG > 0) {
-        const hipError_t e = launch_grid_build(r->R, r->stream, 1);
-        if (e != hipSuccess) return bfail(b, e, "index rebuild");
-    }
     return RVEA_OK;
 }
 

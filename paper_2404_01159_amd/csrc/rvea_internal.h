@@ -57,8 +57,12 @@ hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring);
 // offspring, objective count for the association phases).
 enum BatchPhase {
     BP_PREP, BP_OFFSPRING, BP_OFFSPRING_FIN, BP_ASSOC, BP_RERANK,
-    BP_NEWPOP, BP_ADAPT, BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
+    BP_NEWPOP, BP_ADAPT, BP_GRID_BUCKET, BP_GRID_RANGES, BP_GRID_FILL, BP_GRID_CELLS,
+    BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
+// class of the indexed association launch (runs with an index of V); the
+// full-scan association classes are the objective counts
+constexpr int kIndexedClass = 0x100;
 int batch_phase_class(int phase, const RunView &R);       // template class of a run
 int64_t batch_phase_blocks(int phase, const RunView &R);  // its block count
 int64_t batch_phase_nbx(int phase, const RunView &R);     // row blocks of 2-D phases
@@ -68,6 +72,11 @@ hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span 
                             int64_t blocks, hipStream_t s);
 hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Span *spans,
                                int n, int64_t blocks, hipStream_t s);
+// the index's phases (association of indexed runs, the four build phases):
+// blocks of a run (0 without an index) and the launch
+int64_t grid_phase_blocks(int phase, const RunView &R);
+hipError_t launch_batch_grid(int phase, const RunView *runs, const Span *spans, int n,
+                             int64_t blocks, hipStream_t s);
 hipError_t launch_batch_vectors(int phase, int cls, const RunView *runs, const Span *spans,
                                 int n, int64_t blocks, hipStream_t s);
 

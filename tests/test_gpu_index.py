@@ -1,8 +1,9 @@
 """The indexed association (three objectives) against the full scan through
 the C ABI: the same association, APD (bit for bit) and survivors every
 generation, adaptations included, at small shapes, at the 10,011-vector
-shape, after a host-set V whose index is unscaled, and after a run leaves a
-batch (its index rebuilt for the vectors the batch adapted).  Both paths are
+shape, after a host-set V whose index is unscaled, inside a batch (whose
+phases keep the index rebuilt as each run adapts) and after a run leaves the
+batch.  Both paths are
 also checked against the oracle by the other GPU tests (the index is the
 default for m = 3)."""
 import numpy as np
@@ -107,6 +108,49 @@ def test_index_rebuilt_after_a_batch(P):
     lock(a, b, 6)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_index_in_a_batch_matches_full_scan(P, graphs):
+    """Indexed and full-scan twins advanced in one batch (with other runs of
+    other objective counts): the same selection every tick, adaptations
+    included, and the same state at the end."""
+    specs = [(1, 3, 40, 105, 105, 3, 20), (3, 3, 64, 300, 351, 4, 20),
+             (1, 3, 500, 10011, 10011, 5, 100), (2, 3, 12, 40, 55, 6, 12)]
+    others = [P.Run(2, 2, 31, 60, 64, seed=2, params=P.default_params(t_max=20)),
+              P.Run(3, 5, 130, 126, 126, seed=3, params=P.default_params(t_max=20))]
+    pairs = [twin(P, pb, m, d, N, K, seed, tm) for pb, m, d, N, K, seed, tm in specs]
+    bt = P.Batch(16)
+    bt.set_graphs(graphs)
+    for a, b in pairs:
+        bt.admit(a)
+        bt.admit(b)
+    for r in others:
+        bt.admit(r)
+    for t in range(12):  # adaptations at 2, 4, ... for t_max 20; at 10 for t_max 100
+        print(f"batched index vs scan, tick {t}", flush=True)
+        bt.step()
+        for a, b in pairs:
+            same_selection(a, b, t)
+    bt.synchronize()
+    for a, b in pairs:
+        sa, sb = a.get_state(), b.get_state()
+        for k in ("X", "F", "valid", "V", "gamma"):
+            assert np.array_equal(sa[k], sb[k], equal_nan=True), k
+        assert a.indexed and not b.indexed
+        assert a.counters()["full_rescans"] == 0
+    for a, b in pairs:
+        bt.retire(a)
+        bt.retire(b)
+    for r in others:
+        bt.retire(r)
+    bt.close()
+    for a, b in pairs:
+        lock(a, b, 3)  # the index is current after the batch
+        a.close()
+        b.close()
+    for r in others:
+        r.close()
 
 
 def test_index_switch_and_rejections(P):
