@@ -213,12 +213,14 @@ rvea_status rvea_prepare_generations(rvea_run run, int n);
 rvea_status rvea_set_graphs(rvea_run run, int enable);
 
 /* Association (Alg. 1, Eq. 2) through an index of the reference vectors
- * (1, the default for m = 3) or by a scan of all K vectors per row (0).
- * Both give the same association, angle and APD for every row: the index
- * hands each row a candidate list that holds its vector of largest cosine
- * and every vector tied with it, and the cosines are computed the same way.
- * The index is rebuilt whenever V changes.  RVEA_EUNSUPPORTED to enable it
- * for m != 3; only between generations and outside a batch (RVEA_ESTATE). */
+ * (1, the default for m = 2 and m = 3) or by a scan of all K vectors per row
+ * (0).  Both give the same association, angle and APD for every row: the
+ * index hands each row candidates that include its vector of largest cosine
+ * and every vector tied with it (m = 3: a list per grid cell; m = 2: the
+ * cells of a line walked outward until no further vector can tie), and the
+ * cosines are computed the same way.  The index is rebuilt whenever V
+ * changes.  RVEA_EUNSUPPORTED to enable it for m > 3; only between
+ * generations and outside a batch (RVEA_ESTATE). */
 rvea_status rvea_set_index(rvea_run run, int enable);
 
 /* Copies the run state to host memory (waits for the stream).  Any pointer

@@ -46,6 +46,20 @@
 // has a slot of kSlot records of its own; the cells' ranges of vector
 // positions are allocated by one atomic add per wavefront, so the order of
 // the vectors in memory varies from build to build (no result depends on it).
+//
+// Two objectives.  The index is a line: a direction x >= 0 maps to its share
+// u = (x1 / r1) / (x0 / r0 + x1 / r1) of the scaled simplex (u = j / H for
+// the adapted lattice again) and u to one of G = K equal cells.  In the
+// quadrant the angle of a direction is monotone in u, so a row needs no
+// candidate list: it scans its own cell and the cells on either side, then
+// keeps stepping outward on a side while the cosine to the direction of that
+// side's next cell boundary (moved outward by far more than u's rounding)
+// is not below the best cosine found by more than 1e-12.  Every vector
+// beyond that boundary has a smaller cosine than the boundary direction, so
+// the vector of largest cosine and all vectors tied with it have been seen.
+// A walk past kLineWalk cells on a side, or any vector outside the quadrant
+// (which the bucket leaves out and flags), makes the row scan all vectors
+// (counted).  Eq. 5's gamma is then left to the full pass.
 #include "rvea_dev.h"
 #include "rvea_internal.h"
 
@@ -304,45 +318,95 @@ __device__ __forceinline__ int64_t wave_alloc(int n, unsigned long long *total)
     return (int64_t)base + incl - n;
 }
 
+// ------------------------------------------------------------- line
+constexpr int kLineWalk = 64;        // cells a row steps outward on a side at most
+constexpr double kLineEps = 1e-12;   // outward shift of a boundary's u
+constexpr double kLineTau = 1e-12;   // cosine margin of the stopping test
+
+// share u of a direction x on the scaled simplex and its cell; -1 unless
+// both components are >= 0 and finite with a positive sum
+__device__ __forceinline__ int line_cell_of(double x0, double x1, const double *r, int G,
+                                            double &u)
+{
+    const double a = x0 / r[0], b = x1 / r[1];
+    const double s = a + b;
+    u = b / s;
+    if (!(a >= 0.0 && b >= 0.0 && s > 0.0 && s <= 1.79e308 && u >= 0.0 && u <= 1.0))
+        return -1;
+    const int c = (int)(u * G);
+    return c < G ? c : G - 1;
+}
+
+// binary64 cosine of f (norm nrm) and the direction of share u
+__device__ __forceinline__ double line_bound(double f0, double f1, double nrm, double u,
+                                             const double *r)
+{
+    const double b0 = (1.0 - u) * r[0], b1 = u * r[1];
+    return (f0 * b0 + f1 * b1) / (nrm * sqrt(b0 * b0 + b1 * b1));
+}
+
 // ------------------------------------------------------------- build
 // vectors per cell (counts start at zero: the last build cleared them)
 __device__ __forceinline__ void grid_bucket_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
     const int64_t j = bx * 256 + threadIdx.x;
-    if (j == 0) R.gtot[1] = 0;  // the full gamma pass not needed (yet)
+    if (j == 0) {
+        // the full gamma pass not needed (yet); the line leaves gamma to it
+        R.gtot[1] = R.m == 3 ? 0 : 1;
+        R.gtot[2] = 0;  // no vector outside the line (yet)
+    }
     if (j >= R.K) return;
-    int c = cell_of(R.V[j * 3], R.V[j * 3 + 1], R.V[j * 3 + 2], R.gr, R.gG);
-    if (c < 0) c = 0;  // cannot happen for a nonzero vector >= 0
+    int c;
+    if (R.m == 3) {
+        c = cell_of(R.V[j * 3], R.V[j * 3 + 1], R.V[j * 3 + 2], R.gr, R.gG);
+        if (c < 0) c = 0;  // cannot happen for a nonzero vector >= 0
+    } else {
+        double u;
+        c = line_cell_of(R.V[j * 2], R.V[j * 2 + 1], R.gr, R.gG, u);
+    }
     R.gcell[j] = c;
-    atomicAdd(&R.gcnt[c], 1);
+    if (c >= 0) atomicAdd(&R.gcnt[c], 1);
 }
 
 // each cell's range of positions (one atomic add per wavefront); the
-// counts become the fill cursors
+// counts become the fill cursors (grid: counting up from zero, cleared again
+// by the cells pass; line: counting down to zero)
 __device__ __forceinline__ void grid_ranges_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
     const int64_t c = bx * 256 + threadIdx.x;
-    const int64_t cells = (int64_t)R.gG * R.gG;
+    const int64_t cells = index_cells(R.m, R.gG);
     const int n = c < cells ? R.gcnt[c] : 0;
     const int64_t st = wave_alloc(n, &R.gtot[0]);
     if (c < cells) {
         R.gstart[c] = (int32_t)st;
         R.gnum[c] = n;
-        R.gcnt[c] = 0;
+        if (R.m == 3) R.gcnt[c] = 0;
     }
 }
 
-// vectors into their cells' ranges, with their unit directions
+// vectors into their cells' ranges, with their unit directions (grid) or
+// (v, |v|) (line, whose build ends here: the range allocator cleared)
 __device__ __forceinline__ void grid_fill_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
     const int64_t j = bx * 256 + threadIdx.x;
+    if (R.m != 3 && j == 0) R.gtot[0] = 0;
     if (j >= R.K) return;
     const int c = R.gcell[j];
-    const int64_t p = R.gstart[c] + atomicAdd(&R.gcnt[c], 1);
+    if (c < 0) {  // outside the line: every row scans all vectors
+        R.gtot[2] = 1;
+        return;
+    }
+    const int64_t p = R.m == 3 ? R.gstart[c] + atomicAdd(&R.gcnt[c], 1)
+                               : R.gstart[c] + atomicSub(&R.gcnt[c], 1) - 1;
     R.gvec[p] = (int32_t)j;
+    if (R.m != 3) {
+        reinterpret_cast<double4 *>(R.gvh)[p] =
+            make_double4(R.V[j * 2], R.V[j * 2 + 1], R.vn[j], 0.0);
+        return;
+    }
     const double inv = 1.0 / R.vn[j];
     reinterpret_cast<double4 *>(R.gvh)[p] =
         make_double4(R.V[j * 3] * inv, R.V[j * 3 + 1] * inv, R.V[j * 3 + 2] * inv, 0.0);
@@ -787,6 +851,101 @@ __device__ __forceinline__ void assoc_grid_body(const RunView &R, int64_t bx)
     atomicMin(&R.key[bj], ((ab >> R.kb) << R.kb) | (unsigned long long)i);
 }
 
+// One lane per merged row (two objectives): f' and |f'| as the re-rank forms
+// them, the row's cell on the line, the walk outward (or a scan of every
+// vector if the walk is too long or the line incomplete), then as the
+// re-rank: angle, APD of Eq. 4 and the per-vector minimum of (APD, row).
+__device__ __forceinline__ void assoc_line_body(const RunView &R, int64_t bx)
+{
+    const int64_t i = bx * 256 + threadIdx.x;
+    if (i >= R.M) return;
+    if (!R.mvalid[i]) {
+        R.assoc[i] = -1;
+        R.apd[i] = INFINITY;
+        return;
+    }
+    const int64_t pop = *R.t_done;
+    const uint32_t *zb = zbuf(R, pop + 1);
+    const float *Fm = fm_of(R, pop);
+    const double f0 = (double)Fm[i * 2] - (double)ord_dec(zb[0]);
+    const double f1 = (double)Fm[i * 2 + 1] - (double)ord_dec(zb[1]);
+    double n2 = f0 * f0;
+    n2 = fma(f1, f1, n2);
+    const double nrm = sqrt(n2);
+    if (!(nrm > 0.0)) {  // the row is the ideal point: vector 0, APD 0
+        R.assoc[i] = 0;
+        R.apd[i] = 0.0;
+        atomicMin(&R.key[0], (unsigned long long)i);
+        return;
+    }
+    const int G = R.gG;
+    const double *r = R.gr;
+    double best = -INFINITY;
+    int64_t bj = R.K;
+    double u;
+    const int c = line_cell_of(f0, f1, r, G, u);
+    bool full = c < 0 || R.gtot[2] != 0;
+    if (!full) {
+        const double4 *rec = reinterpret_cast<const double4 *>(R.gvh);
+        // scan one cell's vectors into (best, bj)
+        auto scan = [&](int cc) {
+            const int st = R.gstart[cc], n = R.gnum[cc];
+            for (int e = 0; e < n; ++e) {
+                const double4 v = rec[st + e];
+                const int64_t j = R.gvec[st + e];
+                double s = f0 * v.x;
+                s = fma(f1, v.y, s);
+                const double cv = s / (nrm * v.z);
+                if (cv > best || (cv == best && j < bj)) {
+                    best = cv;
+                    bj = j;
+                }
+            }
+        };
+        scan(c);
+        // the cells on either side always; beyond them while the boundary
+        // direction (moved outward by kLineEps in u) could still tie
+        int lo = c, hi = c, steps = 0;
+        while (lo > 0 && !full) {
+            if (lo < c && line_bound(f0, f1, nrm, (double)lo / G + kLineEps, r) + kLineTau < best)
+                break;
+            scan(--lo);
+            full = ++steps > kLineWalk;
+        }
+        steps = 0;
+        while (hi < G - 1 && !full) {
+            if (hi > c &&
+                line_bound(f0, f1, nrm, (double)(hi + 1) / G - kLineEps, r) + kLineTau < best)
+                break;
+            scan(++hi);
+            full = ++steps > kLineWalk;
+        }
+    }
+    if (full) {
+        best = -INFINITY;
+        bj = R.K;
+        for (int64_t j = 0; j < R.K; ++j) {
+            double s = f0 * R.V[j * 2];
+            s = fma(f1, R.V[j * 2 + 1], s);
+            const double cv = s / (nrm * R.vn[j]);
+            if (cv > best || (cv == best && j < bj)) {
+                best = cv;
+                bj = j;
+            }
+        }
+        atomicAdd(&R.counters[1], 1ull);
+    }
+    if (bj >= R.K) bj = 0;
+    const double gj = R.gamma[bj];
+    const double cc = best > 1.0 ? 1.0 : (best < -1.0 ? -1.0 : best);
+    const double th = acos(cc);
+    const double a = (1.0 + *R.pen * th / gj) * nrm;
+    R.assoc[i] = (int32_t)bj;
+    R.apd[i] = a;
+    const unsigned long long ab = (unsigned long long)__double_as_longlong(a);
+    atomicMin(&R.key[bj], ((ab >> R.kb) << R.kb) | (unsigned long long)i);
+}
+
 // ------------------------------------------------------------- kernels
 __global__ __launch_bounds__(256) void k_grid_bucket(RunView R, int gate)
 {
@@ -805,6 +964,7 @@ __global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
     grid_cells_body(R, blockIdx.x, gate);
 }
 __global__ __launch_bounds__(256) void k_assoc_grid(RunView R) { assoc_grid_body(R, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_assoc_line(RunView R) { assoc_line_body(R, blockIdx.x); }
 
 // batched: blockIdx.x decoded into (run, local block) through the span
 // table; the build phases run for the runs whose vectors changed
@@ -833,33 +993,47 @@ __global__ __launch_bounds__(256) void kb_assoc_grid(const RunView *runs, const 
     const int s = find_span(sp, n, blockIdx.x);
     assoc_grid_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
+__global__ __launch_bounds__(256) void kb_assoc_line(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    assoc_line_body(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
 
 // ------------------------------------------------------------- launchers
 hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force)
 {
     if (R.gG <= 0) return hipSuccess;
     const unsigned vb = (unsigned)((R.K + 255) / 256);
-    const int64_t cells = (int64_t)R.gG * R.gG;
+    const int64_t cells = index_cells(R.m, R.gG);
     k_grid_bucket<<<vb, 256, 0, s>>>(R, force);
     k_grid_ranges<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(R, force);
     k_grid_fill<<<vb, 256, 0, s>>>(R, force);
-    k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, force);
+    if (R.m == 3) k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, force);
     return hipGetLastError();
 }
 
 hipError_t launch_assoc_grid(const RunView &R, hipStream_t s)
 {
-    const int64_t threads = R.M * kGridRowLanes;
-    k_assoc_grid<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(R);
+    if (R.m == 3) {
+        const int64_t threads = R.M * kGridRowLanes;
+        k_assoc_grid<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(R);
+    } else {
+        k_assoc_line<<<(unsigned)((R.M + 255) / 256), 256, 0, s>>>(R);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_batch_grid(int phase, const RunView *runs, const Span *sp, int n,
+hipError_t launch_batch_grid(int phase, int cls, const RunView *runs, const Span *sp, int n,
                              int64_t blocks, hipStream_t s)
 {
     const dim3 g((unsigned)blocks);
     switch (phase) {
-    case BP_ASSOC: kb_assoc_grid<<<g, 256, 0, s>>>(runs, sp, n); break;
+    case BP_ASSOC:
+        if (cls == (kIndexedClass | 3))
+            kb_assoc_grid<<<g, 256, 0, s>>>(runs, sp, n);
+        else
+            kb_assoc_line<<<g, 256, 0, s>>>(runs, sp, n);
+        break;
     case BP_GRID_BUCKET: kb_grid_bucket<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_RANGES: kb_grid_ranges<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_FILL: kb_grid_fill<<<g, 256, 0, s>>>(runs, sp, n); break;
@@ -872,13 +1046,13 @@ hipError_t launch_batch_grid(int phase, const RunView *runs, const Span *sp, int
 int64_t grid_phase_blocks(int phase, const RunView &R)
 {
     if (R.gG <= 0) return 0;
-    const int64_t cells = (int64_t)R.gG * R.gG;
+    const int64_t cells = index_cells(R.m, R.gG);
     switch (phase) {
-    case BP_ASSOC: return (R.M * kGridRowLanes + 255) / 256;
+    case BP_ASSOC: return ((R.m == 3 ? R.M * kGridRowLanes : R.M) + 255) / 256;
     case BP_GRID_BUCKET:
     case BP_GRID_FILL: return (R.K + 255) / 256;
     case BP_GRID_RANGES: return (cells + 255) / 256;
-    case BP_GRID_CELLS: return cells;
+    case BP_GRID_CELLS: return R.m == 3 ? cells : 0;
     }
     return 0;
 }
@@ -887,6 +1061,7 @@ int grid_slot() { return kSlot; }
 
 int grid_side(int m, int64_t K)
 {
+    if (m == 2) return K < 2 ? 2 : (int)K;  // a line of K cells
     if (m != 3) return 0;
     int G = (int)ceil(1.0 * sqrt((double)K));
     return G < 2 ? 2 : G;

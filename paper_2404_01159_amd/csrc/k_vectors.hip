@@ -155,7 +155,7 @@ int batch_phase_class(int phase, const RunView &R)
     if (phase == BP_OFFSPRING)
         return offspring_segment(R.d, R.N) |
                (R.eta_c == 20.0 && R.eta_m == 20.0 ? kDefaultIndices : 0);
-    if (phase == BP_ASSOC && R.gG > 0) return kIndexedClass;
+    if (phase == BP_ASSOC && R.gG > 0) return kIndexedClass | R.m;
     if (phase == BP_ASSOC || phase == BP_RERANK || phase == BP_GAMMA_ASSOC ||
         phase == BP_GAMMA_RERANK)
         return R.m;
@@ -196,9 +196,9 @@ hipError_t launch_batch(int phase, int cls, const RunView *runs, const Span *sp,
 {
     if (phase <= BP_OFFSPRING_FIN) return launch_batch_gen(phase, cls, runs, sp, n, blocks, s);
     if (phase == BP_ADAPT) return launch_batch_vectors(phase, cls, runs, sp, n, blocks, s);
-    if ((phase == BP_ASSOC && cls == kIndexedClass) ||
+    if ((phase == BP_ASSOC && (cls & kIndexedClass)) ||
         (phase >= BP_GRID_BUCKET && phase <= BP_GRID_CELLS))
-        return launch_batch_grid(phase, runs, sp, n, blocks, s);
+        return launch_batch_grid(phase, cls, runs, sp, n, blocks, s);
     return launch_batch_select(phase, cls, runs, sp, n, blocks, s);
 }
 

@@ -58,20 +58,24 @@ struct RunView {
     int op;             // reproduction operator (OP_*)
     double op_a, op_b;  // its parameters
     float *Vel;         // (K+N) x ld velocities by physical row (PSO, CSO), else null
-    // index of the reference vectors (three objectives; k_grid.hip)
-    int gG;             // cells per side of the grid (0: association by full scan)
-    int64_t gcap;       // list records: a slot of equal size per cell
-    double *gr;         // 3: the scaling r the grid's coordinates divide by
-    int32_t *gcell;     // K: cell of each vector
-    int32_t *gcnt;      // G*G: vectors per cell, then fill cursors (build)
-    int32_t *gstart;    // G*G: first position of each cell's vectors
-    int32_t *gnum;      // G*G: vectors of each cell
+    // index of the reference vectors (k_grid.hip): a grid of G x G cells
+    // (three objectives) or a line of G cells (two); "cells" below is G*G or G
+    int gG;             // cells per side (0: association by full scan)
+    int64_t gcap;       // list records: a slot of equal size per cell (grid only)
+    double *gr;         // m: the scaling r the cells' coordinates divide by
+    int32_t *gcell;     // K: cell of each vector (-1: outside the line)
+    int32_t *gcnt;      // cells: vectors per cell, then fill cursors (build)
+    int32_t *gstart;    // cells: first position of each cell's vectors
+    int32_t *gnum;      // cells: vectors of each cell
     int32_t *gvec;      // K: vector ids by cell
-    double *gvh;        // K x 4: their unit directions, by cell
-    int32_t *lcnt;      // G*G: candidate-list length (-1: full scan)
-    int32_t *lstart;    // G*G: first record of each list (-1: full scan)
-    unsigned long long *gtot;  // 2: the allocator of the cells' vector ranges (build),
-                               // and 1 when the build left some vector's gamma
+    double *gvh;        // K x 4: by cell, their unit directions (grid) or
+                        // (v, |v|) (line)
+    int32_t *lcnt;      // cells: candidate-list length (-1: full scan; grid only)
+    int32_t *lstart;    // cells: first record of each list (-1: full scan; grid only)
+    unsigned long long *gtot;  // 4: the allocator of the cells' vector ranges (build),
+                               // 1 when the build left some vector's gamma (always,
+                               // for the line), 1 when some vector is outside the
+                               // line (every row then scans all vectors), spare
     double *lrec;       // gcap x 4: (v, |v|) of the list entries
     int32_t *lidx;      // gcap: vector id of each record
     int32_t *vs;        // K x 2: valid slots, ascending, each with its physical row
@@ -121,6 +125,13 @@ __device__ __forceinline__ float *fm_of(const RunView &R, int64_t p)
 // One run's share of a batched launch: blocks [start, next start) belong to
 // run `run` of the device run table; nbx is the row-block count of a 2-D
 // (row block x vector chunk) phase.
+// cells of an index of side G: a G x G grid for three objectives, a line of
+// G cells for two
+__host__ __device__ inline int64_t index_cells(int m, int G)
+{
+    return m == 3 ? (int64_t)G * G : (int64_t)G;
+}
+
 struct Span {
     int64_t start;
     int32_t run;

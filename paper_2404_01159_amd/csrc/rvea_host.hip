@@ -111,12 +111,13 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, int op, Layout
     L.KC = (int)((K + cs - 1) / cs);
     const int64_t P = (N + 1) / 2;
     L.osplit = op == OP_GA ? offspring_splits(d, N) : 1;
-    // index of the vectors (three objectives): G x G cells, G = sqrt(K)
+    // index of the vectors: for three objectives G x G cells, G = sqrt(K)
     // (about two vectors per cell inside the simplex), each with a slot of
-    // grid_slot() list records (the lists average about eight)
+    // grid_slot() list records (the lists average about eight); for two a
+    // line of G = K cells, no lists
     L.gG = grid_side(m, K);
-    const size_t cells = (size_t)L.gG * L.gG;
-    L.gcap = (int64_t)grid_slot() * (int64_t)cells;
+    const size_t cells = (size_t)index_cells(m, L.gG);
+    L.gcap = m == 3 ? (int64_t)grid_slot() * (int64_t)cells : 0;
     const size_t sz[] = {
         (size_t)(K + N) * L.ld * 4, (size_t)2 * K * 4, (size_t)N * 4, (size_t)2 * K,
         (size_t)2 * M * m * 4, (size_t)M,
@@ -129,7 +130,7 @@ void make_layout(int problem, int m, int d, int64_t N, int64_t K, int op, Layout
         L.osplit > 1 ? (size_t)P * L.osplit * 2 * 8 : 8,
         swarm(op) ? (size_t)(K + N) * L.ld * 4 : 8,
         (size_t)m * 8, (size_t)K * 4, cells * 4, cells * 4, cells * 4, (size_t)K * 4,
-        (size_t)K * 32, cells * 4, cells * 4, 16, (size_t)L.gcap * 32, (size_t)L.gcap * 4};
+        (size_t)K * 32, cells * 4, cells * 4, 32, (size_t)L.gcap * 32, (size_t)L.gcap * 4};
     static_assert(sizeof(sz) / sizeof(sz[0]) == B_COUNT, "one size per buffer");
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
@@ -502,11 +503,11 @@ rvea_status create_run(int problem, int m, int d, int64_t N, int64_t K, uint64_t
     if (e == hipSuccess)
         e = hipMemsetAsync(R.stamp, 0xff, (size_t)(K + N) * 4, r->stream);
     if (e == hipSuccess && R.gG > 0) {  // the index starts unscaled, with no vectors counted
-        e = hipMemcpyAsync(R.gr, kUnitScale, 3 * sizeof(double), hipMemcpyHostToDevice,
+        e = hipMemcpyAsync(R.gr, kUnitScale, (size_t)m * sizeof(double), hipMemcpyHostToDevice,
                            r->stream);
         if (e == hipSuccess)
-            e = hipMemsetAsync(R.gcnt, 0, (size_t)R.gG * R.gG * 4, r->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(R.gtot, 0, 16, r->stream);
+            e = hipMemsetAsync(R.gcnt, 0, (size_t)index_cells(m, R.gG) * 4, r->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(R.gtot, 0, 32, r->stream);
     }
     if (e == hipSuccess) e = launch_lattice(R, r->stream, r->H);
     if (e == hipSuccess) e = launch_gamma(R, r->stream, 1);
@@ -828,7 +829,7 @@ rvea_status rvea_set_state(rvea_run r, const float *X, const float *F, const uin
         HIPCHK(r, launch_gamma(R, r->stream, 1));
     if (V && r->L.gG > 0) {  // a host-set V: the index unscaled and rebuilt
         HIPCHK(r, hipStreamSynchronize(r->stream));
-        HIPCHK(r, hipMemcpy(R.gr, kUnitScale, 3 * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(r, hipMemcpy(R.gr, kUnitScale, (size_t)R.m * sizeof(double), hipMemcpyHostToDevice));
         if (R.gG > 0) HIPCHK(r, launch_grid_build(R, r->stream, 1));
     }
     HIPCHK(r, hipMemcpy(R.t_done, &t, 8, hipMemcpyHostToDevice));

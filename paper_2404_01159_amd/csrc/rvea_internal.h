@@ -39,8 +39,9 @@ hipError_t launch_stamp(const RunView &R, hipStream_t s);
 hipError_t launch_offspring(const RunView &R, hipStream_t s);
 hipError_t launch_operator(const RunView &R, hipStream_t s);  // DE, PSO, CSO, random
 hipError_t launch_assoc(const RunView &R, hipStream_t s);
-// indexed association (three objectives): the index of V, rebuilt when V
-// changes (force, or the adaptation's changed flag), and the association
+// indexed association (two and three objectives): the index of V, rebuilt
+// when V changes (force, or the adaptation's changed flag), and the
+// association
 int grid_side(int m, int64_t K);  // cells per side (0: not indexed)
 int grid_slot();                  // list records per cell
 hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force);
@@ -60,8 +61,8 @@ enum BatchPhase {
     BP_NEWPOP, BP_ADAPT, BP_GRID_BUCKET, BP_GRID_RANGES, BP_GRID_FILL, BP_GRID_CELLS,
     BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
-// class of the indexed association launch (runs with an index of V); the
-// full-scan association classes are the objective counts
+// class of the indexed association launches (runs with an index of V), with
+// the objective count; the full-scan association classes are the counts alone
 constexpr int kIndexedClass = 0x100;
 int batch_phase_class(int phase, const RunView &R);       // template class of a run
 int64_t batch_phase_blocks(int phase, const RunView &R);  // its block count
@@ -75,7 +76,7 @@ hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Sp
 // the index's phases (association of indexed runs, the four build phases):
 // blocks of a run (0 without an index) and the launch
 int64_t grid_phase_blocks(int phase, const RunView &R);
-hipError_t launch_batch_grid(int phase, const RunView *runs, const Span *spans, int n,
+hipError_t launch_batch_grid(int phase, int cls, const RunView *runs, const Span *spans, int n,
                              int64_t blocks, hipStream_t s);
 hipError_t launch_batch_vectors(int phase, int cls, const RunView *runs, const Span *spans,
                                 int n, int64_t blocks, hipStream_t s);

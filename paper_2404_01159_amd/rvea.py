@@ -189,7 +189,7 @@ class Run:
         self.problem, self.m, self.d, self.N, self.K = problem, m, d, N, K
         self.M = K + N
         self.seed = seed
-        self.indexed = m == 3  # the library's default association
+        self.indexed = m in (2, 3)  # the library's default association
         self.params = params if params is not None else default_params()
         self.bytes = footprint(problem, m, d, N, K, self.params)
         dev = torch.device(device)

@@ -1,5 +1,5 @@
-"""The indexed association (three objectives) against the full scan through
-the C ABI: the same association, APD (bit for bit) and survivors every
+"""The indexed association (the grid for three objectives, the line for
+two) against the full scan through the C ABI: the same association, APD (bit for bit) and survivors every
 generation, adaptations included, at small shapes, at the 10,011-vector
 shape, after a host-set V whose index is unscaled, inside a batch (whose
 phases keep the index rebuilt as each run adapts) and after a run leaves the
@@ -54,8 +54,11 @@ def lock(a, b, gens):
 
 
 @pytest.mark.parametrize("case", [(1, 3, 30, 105, 105, 25, 30), (2, 3, 12, 40, 55, 25, 20),
-                                  (3, 3, 64, 300, 351, 21, 20), (1, 3, 10, 3, 3, 12, 10)],
-                         ids=lambda c: "p%d_d%d_N%d_K%d" % (c[0], c[2], c[3], c[4]))
+                                  (3, 3, 64, 300, 351, 21, 20), (1, 3, 10, 3, 3, 12, 10),
+                                  (1, 2, 30, 100, 100, 25, 30), (2, 2, 31, 60, 64, 25, 20),
+                                  (3, 2, 64, 300, 301, 21, 20), (1, 2, 10, 3, 3, 12, 10),
+                                  (2, 2, 20, 2, 2, 8, 10)],
+                         ids=lambda c: "p%d_m%d_d%d_N%d_K%d" % (c[0], c[1], c[2], c[3], c[4]))
 def test_index_matches_full_scan(P, case):
     problem, m, d, N, K, gens, t_max = case
     print(f"index vs scan {case}", flush=True)
@@ -71,6 +74,64 @@ def test_index_matches_full_scan_headline(P):
     a, b = twin(P, 1, 3, 500, 10011, 10011, 3, 100)
     lock(a, b, 12)  # one adaptation (generation 10)
     assert a.counters()["full_rescans"] == 0
+    a.close()
+    b.close()
+
+
+def test_line_index_matches_full_scan_10000_vectors(P):
+    print("line index vs scan at 10,000 vectors", flush=True)
+    a, b = twin(P, 1, 2, 100, 10000, 10000, 3, 100)
+    lock(a, b, 12)  # one adaptation (generation 10)
+    assert a.counters()["full_rescans"] == 0
+    a.close()
+    b.close()
+
+
+def test_line_index_after_host_set_vectors(P):
+    # an adapted-looking V set from the host: the line is rebuilt unscaled
+    import oracle as O
+
+    a, b = twin(P, 2, 2, 20, 200, 200, 11, 40)
+    st = a.get_state()
+    V = O.unit_vectors(O.lattice_H(200, 2), 2) * np.array([30.0, 0.2])
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = st["F"] * np.array([30.0, 0.2], np.float32)
+    for r in (a, b):
+        r.set_state(st["X"], F, st["valid"], V=V, t=0)
+    lock(a, b, 9)
+    a.close()
+    b.close()
+
+
+def test_line_walk_limit_and_outside_vectors_fall_back(P):
+    """Two objectives: vectors crowded near one axis (1 : 1e-3, set from the
+    host, so the line is unscaled) while the rows spread over the quadrant,
+    so most rows step past the walk limit and scan all vectors; then a V with
+    one vector outside the quadrant, which the line leaves out, so every row
+    scans.  The selection equals the full-scan run's throughout (counted
+    rescans)."""
+    import oracle as O
+
+    a, b = twin(P, 1, 2, 16, 300, 301, 9, 50)
+    st = a.get_state()
+    V = O.unit_vectors(O.lattice_H(301, 2), 2) * np.array([1.0, 1e-3])
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    for r in (a, b):
+        r.set_state(st["X"], st["F"], st["valid"], V=V, t=1)
+    lock(a, b, 2)
+    n1 = a.counters()["full_rescans"]
+    assert n1 > 0
+    V2 = O.unit_vectors(O.lattice_H(301, 2), 2)
+    V2[7] = np.array([-0.6, 0.8])
+    st = a.get_state()
+    for r in (a, b):
+        r.set_state(st["X"], st["F"], st["valid"], V=V2, t=1)
+    a.step()
+    b.step()
+    a.select()
+    b.select()
+    same_selection(a, b, 2)
+    assert a.counters()["full_rescans"] - n1 >= 300
     a.close()
     b.close()
 
@@ -116,8 +177,9 @@ def test_index_in_a_batch_matches_full_scan(P, graphs):
     other objective counts): the same selection every tick, adaptations
     included, and the same state at the end."""
     specs = [(1, 3, 40, 105, 105, 3, 20), (3, 3, 64, 300, 351, 4, 20),
-             (1, 3, 500, 10011, 10011, 5, 100), (2, 3, 12, 40, 55, 6, 12)]
-    others = [P.Run(2, 2, 31, 60, 64, seed=2, params=P.default_params(t_max=20)),
+             (1, 3, 500, 10011, 10011, 5, 100), (2, 3, 12, 40, 55, 6, 12),
+             (2, 2, 31, 60, 64, 7, 20), (1, 2, 300, 2000, 2000, 8, 100)]
+    others = [P.Run(1, 8, 31, 60, 120, seed=2, params=P.default_params(t_max=20)),
               P.Run(3, 5, 130, 126, 126, seed=3, params=P.default_params(t_max=20))]
     pairs = [twin(P, pb, m, d, N, K, seed, tm) for pb, m, d, N, K, seed, tm in specs]
     bt = P.Batch(16)
@@ -158,10 +220,16 @@ def test_index_switch_and_rejections(P):
     a.set_index(False)
     a.set_index(True)
     a.generation()
-    p2 = P.Run(1, 2, 20, 10, 10, seed=1)
+    p2 = P.Run(1, 5, 20, 10, 15, seed=1)
     with pytest.raises(P.RveaError):
         p2.set_index(True)
     p2.set_index(False)
+    p3 = P.Run(1, 2, 20, 10, 10, seed=1)
+    assert p3.indexed
+    p3.set_index(False)
+    p3.set_index(True)
+    p3.generation()
+    p3.close()
     a.step()
     with pytest.raises(P.RveaError):
         a.set_index(False)  # between step and select
