@@ -60,6 +60,8 @@
 // A walk past kLineWalk cells on a side, or any vector outside the quadrant
 // (which the bucket leaves out and flags), makes the row scan all vectors
 // (counted).  Eq. 5's gamma is then left to the full pass.
+#include <algorithm>
+
 #include "rvea_dev.h"
 #include "rvea_internal.h"
 
@@ -983,6 +985,8 @@ __global__ __launch_bounds__(256) void kb_grid_fill(const RunView *runs, const S
     const int s = find_span(sp, n, blockIdx.x);
     grid_fill_body(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
 }
+// one cell per workgroup: more per workgroup would keep more registers live
+// in this heavy body, and it is the open generations' cost that matters here
 __global__ __launch_bounds__(64) void kb_grid_cells(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
@@ -1037,7 +1041,9 @@ hipError_t launch_batch_grid(int phase, int cls, const RunView *runs, const Span
     case BP_GRID_BUCKET: kb_grid_bucket<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_RANGES: kb_grid_ranges<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_FILL: kb_grid_fill<<<g, 256, 0, s>>>(runs, sp, n); break;
-    case BP_GRID_CELLS: kb_grid_cells<<<g, 64, 0, s>>>(runs, sp, n); break;
+    case BP_GRID_CELLS:
+        kb_grid_cells<<<g, 64, 0, s>>>(runs, sp, n);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -23,6 +23,8 @@
 //             the next generation's row stamps, block counts and resets
 // Every cross-workgroup combination is an order-free min, so the result
 // does not depend on scheduling.
+#include <algorithm>
+
 #include "rvea_dev.h"
 #include "rvea_internal.h"
 
@@ -790,6 +792,31 @@ __global__ __launch_bounds__(64) void kb_rerank(const RunView *runs, const Span 
     const RunView &R = runs[sp[s].run];
     rerank_body<MD, GAMMA, kBatchRows>(R, blockIdx.x - sp[s].start, R.gG > 0 ? 2 : 0);
 }
+// the batched gamma passes, kSkipBlocks blocks per workgroup (most
+// generations skip them)
+template <int MD, int RR>
+__global__ __launch_bounds__(256) void kb_gamma_assoc(const RunView *runs, const Span *sp, int n,
+                                                      int64_t total)
+{
+    span_blocks<kSkipBlocks>(runs, sp, n, total, gamma_open, [](const RunView &R, int64_t local, int nbx) {
+        assoc_body<MD, RR, true>(R, local % nbx, (int)(local / nbx), 1);
+    });
+}
+// (the re-rank body is called, not inlined: inlined kSkipBlocks times it
+// would keep several times the registers live)
+template <int MD>
+__device__ __attribute__((noinline)) void gamma_rerank_call(const RunView &R, int64_t local)
+{
+    rerank_body<MD, true, kBatchRows>(R, local, 1);
+}
+template <int MD>
+__global__ __launch_bounds__(64) void kb_gamma_rerank(const RunView *runs, const Span *sp, int n,
+                                                      int64_t total)
+{
+    span_blocks<kSkipBlocks>(runs, sp, n, total, gamma_open, [](const RunView &R, int64_t local, int) {
+        gamma_rerank_call<MD>(R, local);
+    });
+}
 __global__ __launch_bounds__(256) void kb_newpop(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
@@ -907,16 +934,20 @@ hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Sp
         RVEA_M_DISPATCH(cls, RVEA_BR);
 #undef RVEA_BR
         break;
-    case BP_GAMMA_ASSOC:
-#define RVEA_BGA(MV) kb_assoc<MV, RR, true><<<g, 256, 0, s>>>(runs, sp, n)
+    case BP_GAMMA_ASSOC: {
+        const dim3 gw((unsigned)((blocks + kSkipBlocks - 1) / kSkipBlocks));
+#define RVEA_BGA(MV) kb_gamma_assoc<MV, RR><<<gw, 256, 0, s>>>(runs, sp, n, blocks)
         RVEA_M_DISPATCH(cls, RVEA_BGA);
 #undef RVEA_BGA
         break;
-    case BP_GAMMA_RERANK:
-#define RVEA_BGR(MV) kb_rerank<MV, true><<<g, 64, 0, s>>>(runs, sp, n)
+    }
+    case BP_GAMMA_RERANK: {
+        const dim3 gw((unsigned)((blocks + kSkipBlocks - 1) / kSkipBlocks));
+#define RVEA_BGR(MV) kb_gamma_rerank<MV><<<gw, 64, 0, s>>>(runs, sp, n, blocks)
         RVEA_M_DISPATCH(cls, RVEA_BGR);
 #undef RVEA_BGR
         break;
+    }
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -122,9 +122,6 @@ __device__ __forceinline__ float *fm_of(const RunView &R, int64_t p)
     return R.Fms + (p & 1) * R.M * R.m;
 }
 
-// One run's share of a batched launch: blocks [start, next start) belong to
-// run `run` of the device run table; nbx is the row-block count of a 2-D
-// (row block x vector chunk) phase.
 // cells of an index of side G: a G x G grid for three objectives, a line of
 // G cells for two
 __host__ __device__ inline int64_t index_cells(int m, int G)
@@ -132,6 +129,9 @@ __host__ __device__ inline int64_t index_cells(int m, int G)
     return m == 3 ? (int64_t)G * G : (int64_t)G;
 }
 
+// One run's share of a batched launch: blocks [start, next start) belong to
+// run `run` of the device run table; nbx is the row-block count of a 2-D
+// (row block x vector chunk) phase.
 struct Span {
     int64_t start;
     int32_t run;
@@ -147,6 +147,45 @@ __device__ __forceinline__ int find_span(const Span *sp, int n, int64_t b)
         if (sp[mid].start <= b) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Batched phases that most generations skip (the index build, the gamma
+// passes) give each workgroup U consecutive blocks of the span table, so a
+// generation in which every run's phase is off (open(R) false) launches U
+// times fewer workgroups (their launch, not their work, is what such a
+// generation pays for).  The U steps are unrolled (a loop around the body
+// keeps far more registers live; so can U inlined copies of a large body,
+// which a caller then keeps out of line).  body(R, local block, nbx); every value
+// that steers the steps is uniform over the workgroup, and a barrier
+// separates one block's use of shared memory from the next.
+template <int U, typename Open, typename Body>
+__device__ __forceinline__ void span_blocks(const RunView *runs, const Span *sp, int n,
+                                            int64_t total, Open open, Body body)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * U;
+    int s = find_span(sp, n, b0), cur = -1;
+    bool on = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t b = b0 + u;
+        if (b >= total) break;
+        while (s + 1 < n && sp[s + 1].start <= b) ++s;
+        if (s != cur) {
+            cur = s;
+            on = open(runs[sp[s].run]);
+        }
+        if (on) {
+            if (u > 0) __syncthreads();
+            body(runs[sp[s].run], b - sp[s].start, sp[s].nbx);
+        }
+    }
+}
+
+// the gamma pass of a run runs after its vectors changed, and, with an
+// index, only when the index build left some vector's gamma
+__device__ __forceinline__ bool gamma_open(const RunView &R)
+{
+    return *R.vchanged != 0 && (R.gG == 0 || R.gtot[1] != 0);
 }
 
 // ---------------------------------------------------------------- Philox

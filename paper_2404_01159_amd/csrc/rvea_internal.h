@@ -61,6 +61,9 @@ enum BatchPhase {
     BP_NEWPOP, BP_ADAPT, BP_GRID_BUCKET, BP_GRID_RANGES, BP_GRID_FILL, BP_GRID_CELLS,
     BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
+// blocks per workgroup of the batched phases that most generations skip
+// (span_blocks)
+constexpr int kSkipBlocks = 8;
 // class of the indexed association launches (runs with an index of V), with
 // the objective count; the full-scan association classes are the counts alone
 constexpr int kIndexedClass = 0x100;
