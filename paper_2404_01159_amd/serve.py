@@ -8,7 +8,8 @@ the arena.  Every tick advances every admitted run by one generation with one
 rvea_batch_step (one launch per phase, replayed as a graph while membership
 is stable); runs that have done their generations leave the batch at the tick
 boundary and free their memory, and queued requests take their place.
-Latency is arrival to completion of the last generation.
+Latency is arrival to completion of the last generation.  Once no request
+is waiting, the ticks up to the next completion are enqueued together.
 
 The loop talks to a backend with five operations (footprint, create, admit,
 retire, step); `DeviceBackend` is the HIP library's.
@@ -127,8 +128,11 @@ class DeviceBackend:
         self._rid.pop(id(run), None)
         run.close()
 
-    def step(self):
-        self.batch.step()
+    # step(n) advances n ticks with one host synchronization at the end
+    multi_tick = True
+
+    def step(self, n=1):
+        self.batch.step(n)
         self.batch.synchronize()
 
 
@@ -167,12 +171,20 @@ class Server:
                     sleep(max(0.0, queue[0].arrival - (clock() - t0)))
                 continue
             self.peak_runs = max(self.peak_runs, len(active))
-            self.backend.step()
-            self.ticks += 1
+            # with nothing left to admit, the ticks up to the next completion
+            # go to the device at once (no host round trip between them)
+            k = 1
+            if not queue and getattr(self.backend, "multi_tick", False):
+                k = min(ent[0].gens - ent[3] for ent in active.values())
+            if k > 1:
+                self.backend.step(k)
+            else:
+                self.backend.step()
+            self.ticks += k
             now = clock() - t0
             for rid in list(active):
                 ent = active[rid]
-                ent[3] += 1
+                ent[3] += k
                 if ent[3] >= ent[0].gens:
                     req, run, off, _, adm = ent
                     self.backend.retire(run)

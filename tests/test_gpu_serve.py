@@ -63,6 +63,8 @@ def test_served_generations_match_oracle(P):
     O.lib()
 
     class CheckedBackend(DeviceBackend):
+        multi_tick = False  # checked tick by tick
+
         def __init__(self, *a, **kw):
             super().__init__(*a, **kw)
             self.live = {}

@@ -99,6 +99,35 @@ def test_memory_pressure_queues_requests():
     assert be.max_seen < 20  # the budget forced queueing
 
 
+def test_multi_tick_steps_keep_generation_counts():
+    """A backend that takes several ticks per step gets them only once no
+    request waits, never past a run's last generation."""
+    clock = FakeClock()
+
+    class MultiBackend(FakeBackend):
+        multi_tick = True
+
+        def __init__(self, clock):
+            super().__init__(clock)
+            self.steps = []
+
+        def step(self, n=1):
+            self.steps.append(n)
+            for _ in range(n):
+                super().step()
+
+    be = MultiBackend(clock)
+    rs = reqs(12, rate=0.0)
+    for i, r in enumerate(rs):
+        rs[i] = Request(r.rid, r.arrival, r.problem, r.m, r.d, r.N, r.K, r.seed, 5 + i % 4)
+    big = max(r.K * r.d * 8 for r in rs)
+    srv = Server(be, 64 * big, max_runs=64)
+    res = srv.serve(rs, clock=clock, sleep=clock.sleep)
+    assert sorted(r.rid for r in res) == list(range(12))
+    assert all(be.gens[r.rid] == r.gens for r in rs)
+    assert max(be.steps) > 1 and srv.ticks == sum(be.steps) == 8
+
+
 def test_oversized_request_is_rejected():
     clock = FakeClock()
     rs = reqs(3, rate=0.0)
