@@ -1295,7 +1295,20 @@ rvea_status rebuild_plan(rvea_batch b)
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     const int n = (int)b->runs.size();
     std::vector<RunView> views(n);
-    for (int i = 0; i < n; ++i) views[i] = b->runs[i]->R;
+    for (int i = 0; i < n; ++i) {
+        views[i] = b->runs[i]->R;
+        // the batch fills the device with many runs, so a run's full-scan
+        // passes need no vector chunks for occupancy: chunks of up to 32
+        // tiles (never more chunks than the run's buffers hold), which cuts
+        // the per-chunk maxima written and re-read and the re-rank's walk
+        // over them (the exact argmax does not depend on the chunking)
+        RunView &v = views[i];
+        const int64_t cs = std::min<int64_t>(32 * kTile, (v.K + kTile - 1) / kTile * kTile);
+        if (cs > v.CS) {
+            v.CS = (int)cs;
+            v.KC = (int)((v.K + cs - 1) / cs);
+        }
+    }
     std::vector<Span> spans;
     b->plan.clear();
     for (int phase = 0; phase < BP_COUNT; ++phase) {
