@@ -349,7 +349,7 @@ rvea_status rvea_destroy(rvea_run run);
  * state and Philox stream, so a run's results do not depend on what else is
  * in the batch.  Adaptation is decided on the device per run.
  *   workspace   device memory of rvea_batch_footprint(max_runs) bytes,
- *               256-byte aligned, owned by the caller (run table and spans)
+ *               256-byte aligned, owned by the caller (run tables and spans)
  *   hip_stream  the stream every batched generation is enqueued on
  * While admitted, a run rejects rvea_step/select/adapt/run_generations and
  * rvea_set_state (RVEA_ESTATE); its accessors wait for the batch stream.

@@ -177,8 +177,9 @@ struct rvea_run_s {
 struct rvea_batch_s {
     int max_runs;
     hipStream_t stream;
-    RunView *d_runs;  // max_runs views, device
-    Span *d_spans;    // BP_COUNT * max_runs spans, device
+    RunView *d_runs;    // max_runs views, device
+    RunView *d_gruns;   // the same views with the gamma pass's vector chunks, device
+    Span *d_spans;      // BP_COUNT * max_runs spans, device
     std::vector<rvea_run> runs;
     struct Launch {
         int phase, cls;
@@ -1294,9 +1295,14 @@ rvea_status rebuild_plan(rvea_batch b)
 {
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     const int n = (int)b->runs.size();
-    std::vector<RunView> views(n);
+    std::vector<RunView> views(n), gviews(n);
     for (int i = 0; i < n; ++i) {
         views[i] = b->runs[i]->R;
+        // the gamma passes (rows = vectors) keep the run's own chunking, as
+        // alone: their few rows need the chunks for parallelism
+        gviews[i] = views[i];
+        gviews[i].KC = gviews[i].gKC;
+        gviews[i].CS = gviews[i].gCS;
         // the batch fills the device with many runs, so a run's full-scan
         // passes need no vector chunks for occupancy: chunks of up to 32
         // tiles (never more chunks than the run's buffers hold), which cuts
@@ -1313,18 +1319,19 @@ rvea_status rebuild_plan(rvea_batch b)
     b->plan.clear();
     for (int phase = 0; phase < BP_COUNT; ++phase) {
         std::vector<int> classes;
+        const std::vector<RunView> &pv = batch_phase_gamma(phase) ? gviews : views;
         for (int i = 0; i < n; ++i) {
-            const int c = batch_phase_class(phase, views[i]);
+            const int c = batch_phase_class(phase, pv[i]);
             if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
         }
         std::sort(classes.begin(), classes.end());
         for (int c : classes) {
             rvea_batch_s::Launch L{phase, c, (int64_t)spans.size(), 0, 0};
             for (int i = 0; i < n; ++i) {
-                if (batch_phase_class(phase, views[i]) != c) continue;
-                const int64_t nb = batch_phase_blocks(phase, views[i]);
+                if (batch_phase_class(phase, pv[i]) != c) continue;
+                const int64_t nb = batch_phase_blocks(phase, pv[i]);
                 if (nb <= 0) continue;
-                spans.push_back(Span{L.blocks, i, (int32_t)batch_phase_nbx(phase, views[i])});
+                spans.push_back(Span{L.blocks, i, (int32_t)batch_phase_nbx(phase, pv[i])});
                 L.blocks += nb;
                 ++L.n;
             }
@@ -1333,6 +1340,7 @@ rvea_status rebuild_plan(rvea_batch b)
     }
     if (n > 0) {
         BHIPCHK(b, hipMemcpy(b->d_runs, views.data(), sizeof(RunView) * n, hipMemcpyHostToDevice));
+        BHIPCHK(b, hipMemcpy(b->d_gruns, gviews.data(), sizeof(RunView) * n, hipMemcpyHostToDevice));
         BHIPCHK(b, hipMemcpy(b->d_spans, spans.data(), sizeof(Span) * spans.size(),
                              hipMemcpyHostToDevice));
     }
@@ -1344,8 +1352,8 @@ rvea_status rebuild_plan(rvea_batch b)
 hipError_t enqueue_batch_generation(rvea_batch b, hipStream_t s)
 {
     for (const auto &L : b->plan) {
-        hipError_t e = launch_batch(L.phase, L.cls, b->d_runs, b->d_spans + L.span_off, L.n,
-                                    L.blocks, s);
+        hipError_t e = launch_batch(L.phase, L.cls, batch_phase_gamma(L.phase) ? b->d_gruns : b->d_runs,
+                                    b->d_spans + L.span_off, L.n, L.blocks, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1358,7 +1366,7 @@ rvea_status rvea_batch_footprint(int max_runs, size_t *bytes)
     if (!bytes || max_runs < 1 || max_runs > (1 << 16)) return RVEA_EINVAL;
     const size_t a = ((size_t)max_runs * sizeof(RunView) + 255) / 256 * 256;
     const size_t c = ((size_t)BP_COUNT * max_runs * sizeof(Span) + 255) / 256 * 256;
-    *bytes = a + c;
+    *bytes = 2 * a + c;
     return RVEA_OK;
 }
 
@@ -1375,9 +1383,10 @@ rvea_status rvea_batch_create(int max_runs, void *workspace, size_t workspace_by
     rvea_batch b = new rvea_batch_s();
     b->max_runs = max_runs;
     b->stream = (hipStream_t)hip_stream;
+    const size_t a = ((size_t)max_runs * sizeof(RunView) + 255) / 256 * 256;
     b->d_runs = (RunView *)workspace;
-    b->d_spans = (Span *)((char *)workspace +
-                          ((size_t)max_runs * sizeof(RunView) + 255) / 256 * 256);
+    b->d_gruns = (RunView *)((char *)workspace + a);
+    b->d_spans = (Span *)((char *)workspace + 2 * a);
     *out = b;
     return RVEA_OK;
 }

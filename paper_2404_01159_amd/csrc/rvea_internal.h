@@ -67,6 +67,11 @@ constexpr int kSkipBlocks = 8;
 // class of the indexed association launches (runs with an index of V), with
 // the objective count; the full-scan association classes are the counts alone
 constexpr int kIndexedClass = 0x100;
+// the gamma passes run over a view with the gamma pass's own vector chunks
+inline bool batch_phase_gamma(int phase)
+{
+    return phase == BP_GAMMA_ASSOC || phase == BP_GAMMA_RERANK;
+}
 int batch_phase_class(int phase, const RunView &R);       // template class of a run
 int64_t batch_phase_blocks(int phase, const RunView &R);  // its block count
 int64_t batch_phase_nbx(int phase, const RunView &R);     // row blocks of 2-D phases
