@@ -792,29 +792,34 @@ __global__ __launch_bounds__(64) void kb_rerank(const RunView *runs, const Span 
     const RunView &R = runs[sp[s].run];
     rerank_body<MD, GAMMA, kBatchRows>(R, blockIdx.x - sp[s].start, R.gG > 0 ? 2 : 0);
 }
-// the batched gamma passes, kSkipBlocks blocks per workgroup (most
-// generations skip them)
-template <int MD, int RR>
+// the batched gamma passes, U blocks per workgroup (U = kSkipBlocks when
+// the launch has blocks enough to fill the device U times over: most
+// generations skip them; else 1, so that a few runs' pass keeps its
+// parallelism in the generations that run it)
+template <int MD, int RR, int U>
 __global__ __launch_bounds__(256) void kb_gamma_assoc(const RunView *runs, const Span *sp, int n,
                                                       int64_t total)
 {
-    span_blocks<kSkipBlocks>(runs, sp, n, total, gamma_open, [](const RunView &R, int64_t local, int nbx) {
+    span_blocks<U>(runs, sp, n, total, gamma_open, [](const RunView &R, int64_t local, int nbx) {
         assoc_body<MD, RR, true>(R, local % nbx, (int)(local / nbx), 1);
     });
 }
-// (the re-rank body is called, not inlined: inlined kSkipBlocks times it
+// (with U > 1 the re-rank body is called, not inlined: inlined U times it
 // would keep several times the registers live)
 template <int MD>
 __device__ __attribute__((noinline)) void gamma_rerank_call(const RunView &R, int64_t local)
 {
     rerank_body<MD, true, kBatchRows>(R, local, 1);
 }
-template <int MD>
+template <int MD, int U>
 __global__ __launch_bounds__(64) void kb_gamma_rerank(const RunView *runs, const Span *sp, int n,
                                                       int64_t total)
 {
-    span_blocks<kSkipBlocks>(runs, sp, n, total, gamma_open, [](const RunView &R, int64_t local, int) {
-        gamma_rerank_call<MD>(R, local);
+    span_blocks<U>(runs, sp, n, total, gamma_open, [](const RunView &R, int64_t local, int) {
+        if constexpr (U == 1)
+            rerank_body<MD, true, kBatchRows>(R, local, 1);
+        else
+            gamma_rerank_call<MD>(R, local);
     });
 }
 __global__ __launch_bounds__(256) void kb_newpop(const RunView *runs, const Span *sp, int n)
@@ -934,18 +939,23 @@ hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Sp
         RVEA_M_DISPATCH(cls, RVEA_BR);
 #undef RVEA_BR
         break;
-    case BP_GAMMA_ASSOC: {
-        const dim3 gw((unsigned)((blocks + kSkipBlocks - 1) / kSkipBlocks));
-#define RVEA_BGA(MV) kb_gamma_assoc<MV, RR><<<gw, 256, 0, s>>>(runs, sp, n, blocks)
-        RVEA_M_DISPATCH(cls, RVEA_BGA);
-#undef RVEA_BGA
-        break;
-    }
+    case BP_GAMMA_ASSOC:
     case BP_GAMMA_RERANK: {
-        const dim3 gw((unsigned)((blocks + kSkipBlocks - 1) / kSkipBlocks));
-#define RVEA_BGR(MV) kb_gamma_rerank<MV><<<gw, 64, 0, s>>>(runs, sp, n, blocks)
-        RVEA_M_DISPATCH(cls, RVEA_BGR);
+        const bool wide = blocks >= (int64_t)kSkipBlocks * kFillBlocks;
+        const dim3 gw((unsigned)(wide ? (blocks + kSkipBlocks - 1) / kSkipBlocks : blocks));
+        if (phase == BP_GAMMA_ASSOC) {
+#define RVEA_BGA(MV)                                                                   \
+    (wide ? kb_gamma_assoc<MV, RR, kSkipBlocks><<<gw, 256, 0, s>>>(runs, sp, n, blocks) \
+          : kb_gamma_assoc<MV, RR, 1><<<gw, 256, 0, s>>>(runs, sp, n, blocks))
+            RVEA_M_DISPATCH(cls, RVEA_BGA);
+#undef RVEA_BGA
+        } else {
+#define RVEA_BGR(MV)                                                                \
+    (wide ? kb_gamma_rerank<MV, kSkipBlocks><<<gw, 64, 0, s>>>(runs, sp, n, blocks) \
+          : kb_gamma_rerank<MV, 1><<<gw, 64, 0, s>>>(runs, sp, n, blocks))
+            RVEA_M_DISPATCH(cls, RVEA_BGR);
 #undef RVEA_BGR
+        }
         break;
     }
     default: return hipErrorInvalidValue;

@@ -1295,7 +1295,8 @@ rvea_status rebuild_plan(rvea_batch b)
 {
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     const int n = (int)b->runs.size();
-    std::vector<RunView> views(n), gviews(n);
+    std::vector<RunView> views(n), gviews(n), wide(n);
+    int64_t wide_blocks = 0;
     for (int i = 0; i < n; ++i) {
         views[i] = b->runs[i]->R;
         // the gamma passes (rows = vectors) keep the run's own chunking, as
@@ -1303,18 +1304,21 @@ rvea_status rebuild_plan(rvea_batch b)
         gviews[i] = views[i];
         gviews[i].KC = gviews[i].gKC;
         gviews[i].CS = gviews[i].gCS;
-        // the batch fills the device with many runs, so a run's full-scan
-        // passes need no vector chunks for occupancy: chunks of up to 32
-        // tiles (never more chunks than the run's buffers hold), which cuts
-        // the per-chunk maxima written and re-read and the re-rank's walk
-        // over them (the exact argmax does not depend on the chunking)
-        RunView &v = views[i];
+        // a batch whose runs fill the device by themselves needs no vector
+        // chunks for occupancy: chunks of up to 32 tiles (never more chunks
+        // than the run's buffers hold) cut the per-chunk maxima written and
+        // re-read and the re-rank's walk over them (the exact argmax does not
+        // depend on the chunking)
+        RunView &v = wide[i];
+        v = views[i];
         const int64_t cs = std::min<int64_t>(32 * kTile, (v.K + kTile - 1) / kTile * kTile);
         if (cs > v.CS) {
             v.CS = (int)cs;
             v.KC = (int)((v.K + cs - 1) / cs);
         }
+        if (v.gG <= 0) wide_blocks += batch_phase_blocks(BP_ASSOC, v);
     }
+    if (wide_blocks >= kFillBlocks) views = wide;
     std::vector<Span> spans;
     b->plan.clear();
     for (int phase = 0; phase < BP_COUNT; ++phase) {

@@ -62,8 +62,10 @@ enum BatchPhase {
     BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
 // blocks per workgroup of the batched phases that most generations skip
-// (span_blocks)
+// (span_blocks), used by launches of at least kSkipBlocks * kFillBlocks
+// blocks; kFillBlocks workgroups fill the device several times over
 constexpr int kSkipBlocks = 8;
+constexpr int64_t kFillBlocks = 2048;
 // class of the indexed association launches (runs with an index of V), with
 // the objective count; the full-scan association classes are the counts alone
 constexpr int kIndexedClass = 0x100;
