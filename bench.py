@@ -398,6 +398,20 @@ def serving_legs(a):
     out["open_loop"] = dict(latency_summary(res), arena_gib=a.serve_budget_gib,
                             peak_resident_runs=srv.peak_runs, ticks=srv.ticks)
     del be, srv
+    # the same runs arriving faster (Poisson serve_rate_high/s, below the
+    # batched capacity): many runs resident at once, in a 16 GiB arena
+    if a.serve_rate_high > 0:
+        hs = serving_specs(a.serve_runs, a.serve_rate_high, seed=0)
+        hreqs = [Request(s["rid"], s["arrival"], s["problem"], s["m"], s["d"], s["N"], s["K"],
+                         s["seed"], s["gens"]) for s in hs]
+        hb = 16 << 30
+        be = DeviceBackend(hb, max_runs=256)
+        srv = Server(be, hb, max_runs=256)
+        res = srv.serve(hreqs)
+        out["open_loop_high_rate"] = dict(latency_summary(res), rate_per_s=a.serve_rate_high,
+                                          arena_gib=16, peak_resident_runs=srv.peak_runs,
+                                          ticks=srv.ticks)
+        del be, srv
     # saturated: every request present at t = 0, large arena
     sat = [Request(r.rid, 0.0, r.problem, r.m, r.d, r.N, r.K, r.seed, r.gens) for r in reqs]
     total = sum(P.footprint(r.problem, r.m, r.d, r.N, r.K, P.default_params()) for r in sat)
@@ -450,6 +464,8 @@ def main():
     ap.add_argument("--serve-runs", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
+    ap.add_argument("--serve-rate-high", type=float, default=400.0,
+                    help="arrival rate of the second open-loop run (0: skip it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
