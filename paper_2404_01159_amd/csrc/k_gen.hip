@@ -482,6 +482,7 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
         const int qn = ns == 1 ? Q : (Q + ns - 1) / ns;
         const int qa = sp * qn, qb = qa + qn < Q ? qa + qn : Q;
         const double lb = R.lb, ub = R.ub;
+        const float flb = (float)lb, fub = (float)ub;
         const double np1 = R.eta_c + 1.0;
         const int nroot =
             NR > 0 ? NR : (np1 >= 1.0 && np1 <= 64.0 && np1 == (double)(int)np1) ? (int)np1 : 0;
@@ -535,23 +536,23 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
             const float pb[4] = {xb.x, xb.y, xb.z, xb.w};
             const W4 w = draw(R, (uint32_t)q, (uint32_t)p, t, TAG_SBX);
             const int g0 = 4 * q;
-            double c1v[4], c2v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t word = w.w[k];
-                const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
-                double B = sgn * sbx_beta<NR>(unif24(word), R.eta_c, nroot);
-                if (((word >> 6) & 1u) || nocross) B = 1.0;
-                const double xa_ = (double)pa[k], xb_ = (double)pb[k];
-                const double up = 1.0 + B, dn = 1.0 - B;
-                c1v[k] = dclip((up * xa_ + dn * xb_) / 2.0, lb, ub);
-                c2v[k] = dclip((dn * xa_ + up * xb_) / 2.0, lb, ub);
-            }
+            // children ((1 +- B) x1 + (1 -+ B) x2) / 2 in binary64 as
+            // (x1 + x2)/2 +- (B/2)(x1 - x2): one rounding from the sum and
+            // difference, within a few ulps of the product form (B = 1, a
+            // copy, is exact), then rounded to binary32 and clipped there
+            // (the same result as clipping in binary64 first, since rounding
+            // to binary32 is monotone)
             float y1[4], y2[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                y1[k] = (float)c1v[k];
-                y2[k] = (float)c2v[k];
+                const uint32_t word = w.w[k];
+                const double hs = ((word >> 7) & 1u) ? 0.5 : -0.5;
+                double hB = hs * sbx_beta<NR>(unif24(word), R.eta_c, nroot);
+                if (((word >> 6) & 1u) || nocross) hB = 0.5;
+                const double xa_ = (double)pa[k], xb_ = (double)pb[k];
+                const double hm = 0.5 * (xa_ + xb_), dd = xa_ - xb_;
+                y1[k] = fminf(fmaxf((float)fma(hB, dd, hm), flb), fub);
+                y2[k] = fminf(fmaxf((float)fma(-hB, dd, hm), flb), fub);
             }
             // genes of this quad that are mutation sites take their mutated
             // values (the sites ascend, so each cursor moves forward only)
