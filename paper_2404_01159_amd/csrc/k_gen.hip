@@ -509,12 +509,11 @@ __device__ __forceinline__ void offspring_body(const RunView &R, int64_t bx)
                 const int kk = g & 3;
                 const uint32_t word = kk == 0 ? w.w[0] : kk == 1 ? w.w[1] : kk == 2 ? w.w[2] : w.w[3];
                 const double xa_ = (double)x1row[g], xb_ = (double)x2row[g];
-                const double sgn = ((word >> 7) & 1u) ? 1.0 : -1.0;
-                double B = sgn * sbx_beta<NR>(unif24(word), R.eta_c, nroot);
-                if (((word >> 6) & 1u) || nocross) B = 1.0;
-                const double up = 1.0 + B, dn = 1.0 - B;
-                const double a1 = c == 0 ? up : dn, a2 = c == 0 ? dn : up;
-                const double x = dclip((a1 * xa_ + a2 * xb_) / 2.0, lb, ub);
+                const double hs = ((word >> 7) & 1u) ? 0.5 : -0.5;
+                double hB = hs * sbx_beta<NR>(unif24(word), R.eta_c, nroot);
+                if (((word >> 6) & 1u) || nocross) hB = 0.5;
+                const double hm = 0.5 * (xa_ + xb_), dd = xa_ - xb_;
+                const double x = dclip(fma(c == 0 ? hB : -hB, dd, hm), lb, ub);
                 const double mg = sh_mags[seg][c][k];
                 sh_vals[seg][c][k] =
                     (float)dclip(x + pm_delta<NR>(x, lb, ub, mg, R.eta_m, nroot_m), lb, ub);
