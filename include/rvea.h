@@ -90,8 +90,8 @@ typedef enum rvea_problem {
  *   RVEA_OP_RAND every child drawn uniformly in the box (the study's
  *                baseline); op_a = op_b = 0.
  * Random draws come from the run's Philox4x32-10 streams; the exact
- * counters are stated in the library's oracle.  Operators other than GA
- * run as single runs only (rvea_batch_admit returns RVEA_EUNSUPPORTED). */
+ * counters are stated in the library's oracle.  Runs of every operator can
+ * join a batch (runs of one operator and segment width share a launch). */
 typedef enum rvea_operator {
     RVEA_OP_GA = 0,
     RVEA_OP_DE = 1,

@@ -290,6 +290,16 @@ __global__ __launch_bounds__(kOffBlock) void k_operator(RunView R)
     operator_body<S, OP>(R, blockIdx.x);
 }
 
+// batched: blockIdx.x decoded into (run, local block) through the span
+// table; the runs of one launch share the operator and the segment width
+template <int S, int OP>
+__global__ __launch_bounds__(kOffBlock) void kb_operator(const RunView *runs, const Span *sp,
+                                                         int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    operator_body<S, OP>(runs[sp[s].run], blockIdx.x - sp[s].start);
+}
+
 template <int OP>
 static void launch_operator_as(const RunView &R, hipStream_t s)
 {
@@ -303,6 +313,46 @@ static void launch_operator_as(const RunView &R, hipStream_t s)
     case 32: k_operator<32, OP><<<g, kOffBlock, 0, s>>>(R); break;
     default: k_operator<64, OP><<<g, kOffBlock, 0, s>>>(R); break;
     }
+}
+
+template <int OP>
+static void launch_batch_operator_as(int S, const RunView *runs, const Span *sp, int n,
+                                     const dim3 g, hipStream_t s)
+{
+    switch (S) {
+    case 4: kb_operator<4, OP><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;
+    case 8: kb_operator<8, OP><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;
+    case 16: kb_operator<16, OP><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;
+    case 32: kb_operator<32, OP><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;
+    default: kb_operator<64, OP><<<g, kOffBlock, 0, s>>>(runs, sp, n); break;
+    }
+}
+
+int operator_class(const RunView &R)
+{
+    return kOperatorClass | (R.op << 8) | pick_segment(R.d);
+}
+
+int64_t operator_blocks(const RunView &R)
+{
+    const int S = pick_segment(R.d);
+    const int64_t units = R.op == OP_CSO ? (R.N + 1) / 2 : R.N;
+    return (units + kOffBlock / S - 1) / (kOffBlock / S);
+}
+
+hipError_t launch_batch_operator(int cls, const RunView *runs, const Span *sp, int n,
+                                 int64_t blocks, hipStream_t s)
+{
+    const dim3 g((unsigned)blocks);
+    const int S = cls & kSegMask;
+    switch ((cls >> 8) & 0xff) {
+    case OP_DE: launch_batch_operator_as<OP_DE>(S, runs, sp, n, g, s); break;
+    case OP_PSO: launch_batch_operator_as<OP_PSO>(S, runs, sp, n, g, s); break;
+    case OP_CSO: launch_batch_operator_as<OP_CSO>(S, runs, sp, n, g, s); break;
+    case OP_RAND: launch_batch_operator_as<OP_RAND>(S, runs, sp, n, g, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_operator(const RunView &R, hipStream_t s)

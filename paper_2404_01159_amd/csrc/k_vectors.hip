@@ -152,6 +152,7 @@ hipError_t launch_batch_vectors(int phase, int cls, const RunView *runs, const S
 // block counts and template classes of the batched phases
 int batch_phase_class(int phase, const RunView &R)
 {
+    if (phase == BP_OFFSPRING && R.op != OP_GA) return operator_class(R);
     if (phase == BP_OFFSPRING)
         return offspring_segment(R.d, R.N) |
                (R.eta_c == 20.0 && R.eta_m == 20.0 ? kDefaultIndices : 0);
@@ -176,6 +177,7 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
     switch (phase) {
     case BP_PREP: return (R.K + R.N + 255) / 256;
     case BP_OFFSPRING: {
+        if (R.op != OP_GA) return operator_blocks(R);
         const int S = offspring_segment(R.d, R.N);
         return ((R.N + 1) / 2 * R.osplit + (kOffBlock / S) - 1) / (kOffBlock / S);
     }
@@ -194,6 +196,8 @@ int64_t batch_phase_blocks(int phase, const RunView &R)
 hipError_t launch_batch(int phase, int cls, const RunView *runs, const Span *sp, int n,
                         int64_t blocks, hipStream_t s)
 {
+    if (phase == BP_OFFSPRING && (cls & kOperatorClass))
+        return launch_batch_operator(cls, runs, sp, n, blocks, s);
     if (phase <= BP_OFFSPRING_FIN) return launch_batch_gen(phase, cls, runs, sp, n, blocks, s);
     if (phase == BP_ADAPT) return launch_batch_vectors(phase, cls, runs, sp, n, blocks, s);
     if ((phase == BP_ASSOC && (cls & kIndexedClass)) ||

@@ -1399,7 +1399,7 @@ rvea_status rvea_batch_admit(rvea_batch b, rvea_run r)
 {
     if (!b || !r) return RVEA_EINVAL;
     if (r->batch || r->phase != 0 || r->timing) return RVEA_ESTATE;
-    if (r->R.problem == kPolicy || r->R.op != OP_GA) return RVEA_EUNSUPPORTED;
+    if (r->R.problem == kPolicy) return RVEA_EUNSUPPORTED;
     if ((int)b->runs.size() >= b->max_runs) return RVEA_ENOMEM;
     // the run's pending work (creation, earlier generations) precedes the batch
     HIPCHK(r, hipStreamSynchronize(r->stream));

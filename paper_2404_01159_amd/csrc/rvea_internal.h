@@ -38,6 +38,14 @@ hipError_t launch_stamp(const RunView &R, hipStream_t s);
 // or launch_operator for the others)
 hipError_t launch_offspring(const RunView &R, hipStream_t s);
 hipError_t launch_operator(const RunView &R, hipStream_t s);  // DE, PSO, CSO, random
+// batched reproduction of the runs with another operator: their template
+// class (kOperatorClass, the operator, the segment width), block count and
+// launch
+constexpr int kOperatorClass = 0x10000;
+int operator_class(const RunView &R);
+int64_t operator_blocks(const RunView &R);
+hipError_t launch_batch_operator(int cls, const RunView *runs, const Span *spans, int n,
+                                 int64_t blocks, hipStream_t s);
 hipError_t launch_assoc(const RunView &R, hipStream_t s);
 // indexed association (two and three objectives): the index of V, rebuilt
 // when V changes (force, or the adaptation's changed flag), and the

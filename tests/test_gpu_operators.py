@@ -189,15 +189,105 @@ def test_operator_full_size_generation(P, O, op):
     run.close()
 
 
-def test_operators_stay_out_of_batches(P):
-    b = P.Batch(4)
-    r = P.Run(1, 3, 50, 105, 105, seed=1, params=P.default_params("de"))
-    with pytest.raises(P.RveaError) as e:
-        b.admit(r)
-    assert e.value.status == P.RVEA_EUNSUPPORTED
+def check_op_generation(P, O, run, prm, st, vel, stats):
+    """One completed generation of an operator run (stepped alone or in a
+    batch) against the oracle from its state before: genes and velocities
+    bit for bit, objectives, the CSO pair report, then selection, the new
+    population, the adaptation and the survivors' velocities."""
+    N = run.N
+    swarm = prm.op in (P.OP_PSO, P.OP_CSO)
+    t = st["t"] + 1
+    off = run.get_offspring()
+    Xo, Vo = O.reproduce_op(ora_params(O, prm), ora_op(O, prm), run.seed, t, st["X"], vel,
+                            st["valid"], st["F"].astype(np.float64), N)
+    bad = np.nonzero(off["X"].view(np.uint32) != Xo.view(np.uint32))
+    assert len(bad[0]) == 0, f"genes differ at t={t}: first {bad[0][:5]}, {bad[1][:5]}"
+    stats["genes"] += Xo.size
+    if swarm:
+        offv = run.get_velocities(offspring=True)
+        assert np.array_equal(offv.view(np.uint32), Vo.view(np.uint32)), \
+            f"velocities differ at t={t}"
+    objectives_close(off["F"], O.evaluate(run.problem, run.m, off["X"]))
+    if prm.op == P.OP_CSO:
+        h = (N + 1) // 2
+        w = off["parents"][:, 0]
+        assert np.array_equal(off["X"][h:], st["X"][w[:N - h]])
+    sel = run.get_selection()
+    st2 = run.get_state()
+    check_after_offspring(O, run, prm, st, off, sel, st2, stats)
+    if swarm:
+        vel2 = run.get_velocities()
+        s = sel["surv"]
+        ok = s >= 0
+        Vm = np.vstack([vel, offv])
+        assert np.array_equal(vel2[ok], Vm[s[ok]]) and not vel2[~ok].any()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batched_operators_match_oracle(P, O, graphs):
+    """Runs of every operator (and a genetic run) advanced together by one
+    batch: every batched generation of every operator run against the
+    oracle, stage by stage, from its state before the batch step."""
+    specs = [("de", 1, 3, 100, 105, 105), ("pso", 2, 3, 1001, 51, 55),
+             ("cso", 3, 5, 37, 120, 126), ("rand", 1, 2, 8, 9, 10),
+             ("pso", 1, 3, 64, 90, 91), ("ga", 2, 3, 40, 105, 105)]
+    runs, prms = [], []
+    for op, problem, m, d, N, K in specs:
+        prm = P.default_params(op, t_max=10, fr=0.2)
+        runs.append(P.Run(problem, m, d, N, K, seed=23 + len(runs), params=prm))
+        prms.append(prm)
+    bt = P.Batch(8)
+    bt.set_graphs(graphs)
+    for r in runs:
+        bt.admit(r)
+    stats = new_stats()
+    for tick in range(6):  # adaptations every second generation
+        before = []
+        for r, prm in zip(runs, prms):
+            sw = prm.op in (P.OP_PSO, P.OP_CSO)
+            before.append((r.get_state(), r.get_velocities() if sw else None))
+        print(f"batched operators, tick {tick}", flush=True)
+        bt.step()
+        for r, prm, (st, vel) in zip(runs, prms, before):
+            if prm.op != P.OP_GA:
+                check_op_generation(P, O, r, prm, st, vel, stats)
+    assert stats["near_ties"] <= 1 and stats["adaptations"] >= 5, stats
+    for r in runs:
+        bt.retire(r)
+        r.close()
+    bt.close()
+
+
+def test_batched_operators_equal_alone(P):
+    specs = [("de", 1, 3, 50, 105, 105), ("pso", 3, 3, 70, 91, 91), ("cso", 2, 2, 33, 40, 40),
+             ("rand", 1, 3, 20, 21, 21)]
+    alone, mixed = [], []
+    for op, problem, m, d, N, K in specs:
+        prm = P.default_params(op, t_max=20)
+        alone.append(P.Run(problem, m, d, N, K, seed=7, params=prm))
+        mixed.append(P.Run(problem, m, d, N, K, seed=7, params=prm))
+    for r in alone:
+        r.run(9)
+    bt = P.Batch(4)
+    for r in mixed:
+        bt.admit(r)
+    bt.step(9)
+    bt.synchronize()
+    for a, b in zip(alone, mixed):
+        sa, sb = a.get_state(), b.get_state()
+        for k in ("X", "F", "valid", "V", "gamma", "t"):
+            assert np.array_equal(sa[k], sb[k], equal_nan=True), k
+        if a.params.op in (P.OP_PSO, P.OP_CSO):
+            assert np.array_equal(a.get_velocities(), b.get_velocities())
+    for r in mixed:
+        bt.retire(r)
+    bt.close()
+    for r in alone + mixed:
+        r.close()
+
+
+def test_velocities_only_for_swarms(P):
     g = P.Run(1, 3, 50, 105, 105, seed=1)
     with pytest.raises(P.RveaError):
         g.get_velocities()
-    r.close()
     g.close()
-    b.close()
