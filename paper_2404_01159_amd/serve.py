@@ -71,6 +71,7 @@ class Request:
     K: int
     seed: int
     gens: int
+    op: str = "ga"  # reproduction operator: "ga", "de", "pso", "cso" or "rand"
 
 
 @dataclasses.dataclass
@@ -105,7 +106,7 @@ class DeviceBackend:
         self._rid = {}
 
     def params(self, req):
-        return self.R.default_params(t_max=max(self.t_max, req.gens))
+        return self.R.default_params(req.op, t_max=max(self.t_max, req.gens))
 
     def footprint(self, req):
         return self.R.footprint(req.problem, req.m, req.d, req.N, req.K, self.params(req))
