@@ -392,15 +392,16 @@ def serving_legs(a):
     out = {"workload": f"{len(reqs)} runs, Poisson {a.serve_rate}/s, m in {{2,3,5,8}}, "
                        "d in [30,2000], K=N in [100,10011], 100 generations each"}
     budget = int(a.serve_budget_gib * (1 << 30))
-    be = DeviceBackend(budget, max_runs=256)
-    srv = Server(be, budget, max_runs=256)
-    res = srv.serve(reqs)
-    out["open_loop"] = dict(latency_summary(res), arena_gib=a.serve_budget_gib,
-                            peak_resident_runs=srv.peak_runs, ticks=srv.ticks)
-    del be, srv
+    if not a.batched_only:
+        be = DeviceBackend(budget, max_runs=256)
+        srv = Server(be, budget, max_runs=256)
+        res = srv.serve(reqs)
+        out["open_loop"] = dict(latency_summary(res), arena_gib=a.serve_budget_gib,
+                                peak_resident_runs=srv.peak_runs, ticks=srv.ticks)
+        del be, srv
     # the same runs arriving faster (Poisson serve_rate_high/s, below the
     # batched capacity): many runs resident at once, in a 16 GiB arena
-    if a.serve_rate_high > 0:
+    if a.serve_rate_high > 0 and not a.batched_only:
         hs = serving_specs(a.serve_runs, a.serve_rate_high, seed=0)
         hreqs = [Request(s["rid"], s["arrival"], s["problem"], s["m"], s["d"], s["N"], s["K"],
                          s["seed"], s["gens"]) for s in hs]
@@ -424,6 +425,8 @@ def serving_legs(a):
                                       ticks=srv.ticks, arena_gib=total / (1 << 30))
     del be, srv
     torch.cuda.synchronize()
+    if a.batched_only:
+        return out
     # one run at a time, plain single-run path (multi-generation graphs)
     t0 = time.perf_counter()
     for r in sat:
@@ -466,6 +469,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--serve-rate-high", type=float, default=400.0,
                     help="arrival rate of the second open-loop run (0: skip it)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="serving: only the runs all present at once (for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")

@@ -3,6 +3,7 @@
 usage: python workloads/summarize_rocprof.py stats <kernel_stats.csv> [title]
        python workloads/summarize_rocprof.py trace <kernel_trace.csv> [title]
        python workloads/summarize_rocprof.py pmc <counter_collection.csv> [title]
+       python workloads/summarize_rocprof.py batch <kernel_trace.csv> <ticks>
 
 `trace` groups dispatches by kernel and grid size, which separates the
 workloads of one run (their grids differ).
@@ -54,8 +55,32 @@ def pmc(path):
     return "\n".join(out)
 
 
+def batch(path, ticks):
+    """The batched phase kernels (kb_*) of a run of `ticks` batch steps:
+    per kernel its calls, per-launch times and time per step."""
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.defaultdict(list)
+    for r in rows:
+        if "kb_" not in r["Kernel_Name"]:
+            continue
+        agg[r["Kernel_Name"][:70]].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    tot = sum(sum(v) for v in agg.values())
+    out = ["| kernel | calls | avg us | min us | max us | per step us | share |",
+           "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        out.append("| `%s` | %d | %.1f | %.1f | %.1f | %.1f | %.1f%% |" % (
+            k, len(v), sum(v) / len(v), min(v), max(v), sum(v) / ticks, 100 * sum(v) / tot))
+    out.append("")
+    out.append("batched kernels per step: %.2f ms" % (tot / ticks / 1e3))
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
+    if mode == "batch":
+        print(batch(path, int(sys.argv[3])))
+        sys.exit(0)
     title = sys.argv[3] if len(sys.argv) > 3 else ""
     if title:
         print(f"## {title}\n")
