@@ -63,6 +63,7 @@
 #include <algorithm>
 
 #include "rvea_dev.h"
+#include "rvea_index.h"
 #include "rvea_internal.h"
 
 namespace rvea {
@@ -150,24 +151,6 @@ __device__ __forceinline__ D3 lift(double q1, double q2, const double *r)
     return d3(r[0] * q1, r[1] * q2, r[2] * (1.0 - q1 - q2));
 }
 
-// cell of a direction x >= 0 (x != 0); q pulled onto the simplex if rounding
-// left it just outside.  -1 if the coordinates are not finite.
-__device__ __forceinline__ int cell_of(double x0, double x1, double x2, const double *r, int G)
-{
-    const double y0 = x0 / r[0], y1 = x1 / r[1], y2 = x2 / r[2];
-    const double s = y0 + y1 + y2;
-    double q1 = y0 / s, q2 = y1 / s;
-    if (!(q1 >= 0.0 && q2 >= 0.0 && q1 <= 2.0 && q2 <= 2.0)) return -1;
-    const double t = q1 + q2;
-    if (t > 1.0) {
-        q1 /= t;
-        q2 /= t;
-    }
-    int ci = (int)floor(q1 * G), cj = (int)floor(q2 * G);
-    ci = ci < 0 ? 0 : (ci > G - 1 ? G - 1 : ci);
-    cj = cj < 0 ? 0 : (cj > G - 1 ? G - 1 : cj);
-    return ci * G + cj;
-}
 
 // One cell's geometry, held in LDS by the cell's workgroup: the square
 // [a, a+h] x [b, b+h] clipped to q1 + q2 <= 1 as five vertices in order
@@ -325,19 +308,6 @@ constexpr int kLineWalk = 64;        // cells a row steps outward on a side at m
 constexpr double kLineEps = 1e-12;   // outward shift of a boundary's u
 constexpr double kLineTau = 1e-12;   // cosine margin of the stopping test
 
-// share u of a direction x on the scaled simplex and its cell; -1 unless
-// both components are >= 0 and finite with a positive sum
-__device__ __forceinline__ int line_cell_of(double x0, double x1, const double *r, int G,
-                                            double &u)
-{
-    const double a = x0 / r[0], b = x1 / r[1];
-    const double s = a + b;
-    u = b / s;
-    if (!(a >= 0.0 && b >= 0.0 && s > 0.0 && s <= 1.79e308 && u >= 0.0 && u <= 1.0))
-        return -1;
-    const int c = (int)(u * G);
-    return c < G ? c : G - 1;
-}
 
 // binary64 cosine of f (norm nrm) and the direction of share u
 __device__ __forceinline__ double line_bound(double f0, double f1, double nrm, double u,
@@ -348,7 +318,9 @@ __device__ __forceinline__ double line_bound(double f0, double f1, double nrm, d
 }
 
 // ------------------------------------------------------------- build
-// vectors per cell (counts start at zero: the last build cleared them)
+// vectors per cell (counts start at zero: the last build cleared them); a
+// rebuild after an adaptation skips this pass, the adaptation having
+// counted each vector as it wrote it (k_vectors.hip)
 __device__ __forceinline__ void grid_bucket_body(const RunView &R, int64_t bx, int gate)
 {
     if (!gate && *R.vchanged == 0) return;
@@ -970,11 +942,6 @@ __global__ __launch_bounds__(256) void k_assoc_line(RunView R) { assoc_line_body
 
 // batched: blockIdx.x decoded into (run, local block) through the span
 // table; the build phases run for the runs whose vectors changed
-__global__ __launch_bounds__(256) void kb_grid_bucket(const RunView *runs, const Span *sp, int n)
-{
-    const int s = find_span(sp, n, blockIdx.x);
-    grid_bucket_body(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
-}
 __global__ __launch_bounds__(256) void kb_grid_ranges(const RunView *runs, const Span *sp, int n)
 {
     const int s = find_span(sp, n, blockIdx.x);
@@ -1016,6 +983,17 @@ hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force)
     return hipGetLastError();
 }
 
+hipError_t launch_grid_rebuild(const RunView &R, hipStream_t s)
+{
+    if (R.gG <= 0) return hipSuccess;
+    const unsigned vb = (unsigned)((R.K + 255) / 256);
+    const int64_t cells = index_cells(R.m, R.gG);
+    k_grid_ranges<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(R, 0);
+    k_grid_fill<<<vb, 256, 0, s>>>(R, 0);
+    if (R.m == 3) k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_assoc_grid(const RunView &R, hipStream_t s)
 {
     if (R.m == 3) {
@@ -1038,7 +1016,6 @@ hipError_t launch_batch_grid(int phase, int cls, const RunView *runs, const Span
         else
             kb_assoc_line<<<g, 256, 0, s>>>(runs, sp, n);
         break;
-    case BP_GRID_BUCKET: kb_grid_bucket<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_RANGES: kb_grid_ranges<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_FILL: kb_grid_fill<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_CELLS:
@@ -1055,7 +1032,6 @@ int64_t grid_phase_blocks(int phase, const RunView &R)
     const int64_t cells = index_cells(R.m, R.gG);
     switch (phase) {
     case BP_ASSOC: return ((R.m == 3 ? R.M * kGridRowLanes : R.M) + 255) / 256;
-    case BP_GRID_BUCKET:
     case BP_GRID_FILL: return (R.K + 255) / 256;
     case BP_GRID_RANGES: return (cells + 255) / 256;
     case BP_GRID_CELLS: return R.m == 3 ? cells : 0;

@@ -9,6 +9,7 @@
 //               unchanged if some range is not positive and finite
 //   k_vec_aux   float copy of V (padded rows) and row norms
 #include "rvea_dev.h"
+#include "rvea_index.h"
 #include "rvea_internal.h"
 
 namespace rvea {
@@ -115,6 +116,29 @@ __device__ __forceinline__ void adapt_v_body(const RunView &R, int64_t bx, bool 
         R.V[j * R.m + k] = v[k];
     }
     write_aux(R, j, v);
+    if (R.gG > 0) {
+        // the index rebuild's first step for this vector: its cell under the
+        // new scaling (each thread forms the scaling as thread 0 stores it),
+        // counted (the counts start at zero: the last build cleared them)
+        double gr[kMaxM];
+        double mx = r[0];
+        for (int k = 1; k < R.m; ++k) mx = fmax(mx, r[k]);
+        for (int k = 0; k < R.m; ++k) gr[k] = fmax(r[k] / mx, 1e-6);
+        int c;
+        if (R.m == 3) {
+            c = cell_of(v[0], v[1], v[2], gr, R.gG);
+            if (c < 0) c = 0;  // cannot happen for a nonzero vector >= 0
+        } else {
+            double u;
+            c = line_cell_of(v[0], v[1], gr, R.gG, u);
+        }
+        R.gcell[j] = c;
+        if (c >= 0) atomicAdd(&R.gcnt[c], 1);
+        if (j == 0) {
+            R.gtot[1] = R.m == 3 ? 0 : 1;  // as the bucket pass sets them
+            R.gtot[2] = 0;
+        }
+    }
 }
 
 __global__ void k_adapt_v(RunView R) { adapt_v_body(R, blockIdx.x, false); }
@@ -171,7 +195,7 @@ int64_t batch_phase_nbx(int phase, const RunView &R)
 
 int64_t batch_phase_blocks(int phase, const RunView &R)
 {
-    if (phase >= BP_GRID_BUCKET && phase <= BP_GRID_CELLS) return grid_phase_blocks(phase, R);
+    if (phase >= BP_GRID_RANGES && phase <= BP_GRID_CELLS) return grid_phase_blocks(phase, R);
     if (phase == BP_ASSOC && R.gG > 0) return grid_phase_blocks(phase, R);
     if (phase == BP_RERANK && R.gG > 0) return 0;  // the indexed association ranks in full
     switch (phase) {
@@ -201,7 +225,7 @@ hipError_t launch_batch(int phase, int cls, const RunView *runs, const Span *sp,
     if (phase <= BP_OFFSPRING_FIN) return launch_batch_gen(phase, cls, runs, sp, n, blocks, s);
     if (phase == BP_ADAPT) return launch_batch_vectors(phase, cls, runs, sp, n, blocks, s);
     if ((phase == BP_ASSOC && (cls & kIndexedClass)) ||
-        (phase >= BP_GRID_BUCKET && phase <= BP_GRID_CELLS))
+        (phase >= BP_GRID_RANGES && phase <= BP_GRID_CELLS))
         return launch_batch_grid(phase, cls, runs, sp, n, blocks, s);
     return launch_batch_select(phase, cls, runs, sp, n, blocks, s);
 }
@@ -215,7 +239,7 @@ hipError_t launch_adapt(const RunView &R, hipStream_t s)
     // vector is among a vector's neighbours, and the full pass runs only when
     // some vector is left
     if (R.gG > 0) {
-        e = launch_grid_build(R, s, 0);
+        e = launch_grid_rebuild(R, s);  // the adaptation counted the vectors
         if (e != hipSuccess) return e;
         return launch_gamma(R, s, 2);
     }

@@ -53,6 +53,9 @@ hipError_t launch_assoc(const RunView &R, hipStream_t s);
 int grid_side(int m, int64_t K);  // cells per side (0: not indexed)
 int grid_slot();                  // list records per cell
 hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force);
+// the rebuild after an adaptation, which has already counted each vector
+// into its cell (runs only when the vectors changed)
+hipError_t launch_grid_rebuild(const RunView &R, hipStream_t s);
 hipError_t launch_assoc_grid(const RunView &R, hipStream_t s);
 hipError_t launch_rerank(const RunView &R, hipStream_t s);
 hipError_t launch_select_back(const RunView &R, hipStream_t s);
@@ -66,7 +69,7 @@ hipError_t launch_rollout(const RunView &R, hipStream_t s, bool offspring);
 // offspring, objective count for the association phases).
 enum BatchPhase {
     BP_PREP, BP_OFFSPRING, BP_OFFSPRING_FIN, BP_ASSOC, BP_RERANK,
-    BP_NEWPOP, BP_ADAPT, BP_GRID_BUCKET, BP_GRID_RANGES, BP_GRID_FILL, BP_GRID_CELLS,
+    BP_NEWPOP, BP_ADAPT, BP_GRID_RANGES, BP_GRID_FILL, BP_GRID_CELLS,
     BP_GAMMA_ASSOC, BP_GAMMA_RERANK, BP_COUNT
 };
 // blocks per workgroup of the batched phases that most generations skip
@@ -91,7 +94,8 @@ hipError_t launch_batch_gen(int phase, int cls, const RunView *runs, const Span 
                             int64_t blocks, hipStream_t s);
 hipError_t launch_batch_select(int phase, int cls, const RunView *runs, const Span *spans,
                                int n, int64_t blocks, hipStream_t s);
-// the index's phases (association of indexed runs, the four build phases):
+// the index's phases (association of indexed runs, the three build phases
+// after the adaptation's counting):
 // blocks of a run (0 without an index) and the launch
 int64_t grid_phase_blocks(int phase, const RunView &R);
 hipError_t launch_batch_grid(int phase, int cls, const RunView *runs, const Span *spans, int n,
