@@ -571,16 +571,26 @@ __device__ __forceinline__ void grid_cells_body(const RunView &R, int64_t bx, in
         }
     }
     __syncthreads();
+    // the least distance from u_c to the boundary of the box of cells of
+    // radius k, on lane k <= kStage: for the box test below and, at radius
+    // kStage, for the own vectors' gamma
+    float bsm = INFINITY;
+    if (!full && lane <= kStage) bsm = box_side_min(R, ci, cj, lane, ld3(g.ucf));
     // Eq. 5's gamma of the cell's own vectors: the largest binary64 cosine
     // to another vector that is not parallel to it (cosine below 1, as the
     // full pass computes it), kept when the staged neighbourhood provably
     // holds that vector (the nearest staged one is closer than the
-    // neighbourhood's boundary); otherwise the full gamma pass is asked for
+    // neighbourhood's boundary: every own vector lies within rho of u_c, so
+    // its distance to that boundary is at least u_c's less rho); otherwise
+    // the full gamma pass is asked for
     {
         const int own = kStage * kStageW + kStage;  // the centre cell's lane
         const int oq0 = __builtin_amdgcn_readlane(incl0 - mine0, own);
         const int on = full ? 0 : __builtin_amdgcn_readlane(cnt[0], own);
         bool need = full && __builtin_amdgcn_readlane(cnt[0], own) > 0;
+        const float lo =
+            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bsm), kStage)) - g.rho -
+            kSlack;
         for (int o = oq0; o < oq0 + on; ++o) {  // uniform
             const int32_t id = st.j[o];
             const double vi[3] = {st.rec[o][0], st.rec[o][1], st.rec[o][2]};
@@ -600,9 +610,6 @@ __device__ __forceinline__ void grid_cells_body(const RunView &R, int64_t bx, in
             }
             gb = -wave_fmin(-gb);
             dmin = (float)wave_fmin((double)dmin);
-            float lo = 0.0f;
-            if (lane == 0) lo = box_side_min(R, ci, cj, kStage, ui);
-            lo = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lo)));
             if (dmin < INFINITY && lo > dmin + 2.0f * kSlack) {
                 if (lane == 0) R.gamma[id] = acos(gb < -1.0 ? -1.0 : gb);
             } else {
@@ -628,8 +635,7 @@ __device__ __forceinline__ void grid_cells_body(const RunView &R, int64_t bx, in
     int kc = 0x7fffffff;
     if (!full) {  // lane k: does the box of radius k hold the ball of radius b + rho?
         const int k = lane;
-        const bool ok =
-            k <= kStage && box_side_min(R, ci, cj, k, ld3(g.ucf)) > b + g.rho + 2.0f * kSlack;
+        const bool ok = k <= kStage && bsm > b + g.rho + 2.0f * kSlack;
         kc = wave_imin(ok ? k : 0x7fffffff);
         full = kc == 0x7fffffff;
     }
