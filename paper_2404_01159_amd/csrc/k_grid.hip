@@ -115,21 +115,25 @@ __device__ __forceinline__ F3 funit(const F3 &a)
     const float inv = __builtin_amdgcn_rcpf(fsqrt(fdot(a, a)));
     return f3(a.x * inv, a.y * inv, a.z * inv);
 }
-__device__ __forceinline__ float fchord(const F3 &a, const F3 &b)
+// squared chord, and the chord (minima and maxima of chords are taken on
+// the squares, with one square root at the end: the square root is
+// monotone, so the result moves by at most its last-bit rounding)
+__device__ __forceinline__ float fchord2(const F3 &a, const F3 &b)
 {
     const F3 d = fsub(a, b);
-    return fsqrt(fdot(d, d));
+    return fdot(d, d);
 }
+__device__ __forceinline__ float fchord(const F3 &a, const F3 &b) { return fsqrt(fchord2(a, b)); }
 __device__ float farc_chord(const F3 &u, const F3 &a, const F3 &b, const F3 &n, bool valid)
 {
-    const float ends = fminf(fchord(u, a), fchord(u, b));
-    if (!valid) return ends;
+    const float ends2 = fminf(fchord2(u, a), fchord2(u, b));
+    if (!valid) return fsqrt(ends2);
     const float un = fdot(u, n);
     const F3 w = f3(u.x - un * n.x, u.y - un * n.y, u.z - un * n.z);
     const float wn = fsqrt(fdot(w, w));
     if (wn > 0.0f && fdot(fcross(a, w), n) >= 0.0f && fdot(fcross(w, b), n) >= 0.0f)
-        return fminf(ends, fsqrt(2.0f * un * un * __builtin_amdgcn_rcpf(1.0f + wn)));
-    return ends;
+        return fsqrt(fminf(ends2, 2.0f * un * un * __builtin_amdgcn_rcpf(1.0f + wn)));
+    return fsqrt(ends2);
 }
 __device__ float farc_chord_of(const F3 &u, const F3 &A, const F3 &B)
 {
@@ -606,10 +610,10 @@ __device__ __forceinline__ void grid_cells_body(const RunView &R, int64_t bx, in
                 const double cv = sd / (vni * st.rec[q][3]);
                 if (cv >= 1.0) continue;
                 gb = fmax(gb, cv);
-                dmin = fminf(dmin, fchord(ui, f3(st.vh[q][0], st.vh[q][1], st.vh[q][2])));
+                dmin = fminf(dmin, fchord2(ui, f3(st.vh[q][0], st.vh[q][1], st.vh[q][2])));
             }
             gb = -wave_fmin(-gb);
-            dmin = (float)wave_fmin((double)dmin);
+            dmin = fsqrt((float)wave_fmin((double)dmin));  // the squared minimum's root
             if (dmin < INFINITY && lo > dmin + 2.0f * kSlack) {
                 if (lane == 0) R.gamma[id] = acos(gb < -1.0 ? -1.0 : gb);
             } else {
@@ -625,11 +629,11 @@ __device__ __forceinline__ void grid_cells_body(const RunView &R, int64_t bx, in
             if (abs(st.di[q]) > kNear || abs(st.dj[q]) > kNear) continue;
             const F3 v = f3(st.vh[q][0], st.vh[q][1], st.vh[q][2]);
             float cov = 0.0f;
-            for (int e = 0; e < kNv; ++e) cov = fmaxf(cov, fchord(ld3(g.Xf[e]), v));
-            best = fminf(best, cov);
+            for (int e = 0; e < kNv; ++e) cov = fmaxf(cov, fchord2(ld3(g.Xf[e]), v));
+            best = fminf(best, cov);  // squared
         }
     }
-    best = (float)wave_fmin((double)best);
+    best = fsqrt((float)wave_fmin((double)best));
     full = full || !(best < INFINITY);
     const float b = best + kSlack;
     int kc = 0x7fffffff;
