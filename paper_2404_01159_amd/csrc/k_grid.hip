@@ -59,7 +59,9 @@
 // the vector of largest cosine and all vectors tied with it have been seen.
 // A walk past kLineWalk cells on a side, or any vector outside the quadrant
 // (which the bucket leaves out and flags), makes the row scan all vectors
-// (counted).  Eq. 5's gamma is then left to the full pass.
+// (counted).  Eq. 5's gamma of each vector comes from the same walk, with
+// the vector as the row, itself and the vectors parallel to it skipped; a
+// walk past the limit leaves it to the full pass.
 #include <algorithm>
 
 #include "rvea_dev.h"
@@ -330,8 +332,7 @@ __device__ __forceinline__ void grid_bucket_body(const RunView &R, int64_t bx, i
     if (!gate && *R.vchanged == 0) return;
     const int64_t j = bx * 256 + threadIdx.x;
     if (j == 0) {
-        // the full gamma pass not needed (yet); the line leaves gamma to it
-        R.gtot[1] = R.m == 3 ? 0 : 1;
+        R.gtot[1] = 0;  // the full gamma pass not needed (yet)
         R.gtot[2] = 0;  // no vector outside the line (yet)
     }
     if (j >= R.K) return;
@@ -930,6 +931,63 @@ __device__ __forceinline__ void assoc_line_body(const RunView &R, int64_t bx)
     atomicMin(&R.key[bj], ((ab >> R.kb) << R.kb) | (unsigned long long)i);
 }
 
+// Eq. 5's gamma of each vector on the line (one lane per vector): the walk
+// of the association with the vector as the row, skipping itself and the
+// vectors exactly parallel to it (binary64 cosine 1 or more), as the full
+// gamma pass does; the largest cosine's angle (pi/2 without another
+// vector).  A vector outside the line or a walk past kLineWalk cells on a
+// side asks for the full gamma pass instead.
+__device__ __forceinline__ void line_gamma_body(const RunView &R, int64_t bx, int gate)
+{
+    if (!gate && *R.vchanged == 0) return;
+    const int64_t i = bx * 256 + threadIdx.x;
+    if (i >= R.K) return;
+    const double f0 = R.V[i * 2], f1 = R.V[i * 2 + 1], nrm = R.vn[i];
+    const int G = R.gG;
+    const double *r = R.gr;
+    double u;
+    const int c = line_cell_of(f0, f1, r, G, u);
+    if (c < 0 || R.gtot[2] != 0) {
+        R.gtot[1] = 1;
+        return;
+    }
+    const double4 *rec = reinterpret_cast<const double4 *>(R.gvh);
+    double best = -INFINITY;
+    auto scan = [&](int cc) {
+        const int st = R.gstart[cc], n = R.gnum[cc];
+        for (int e = 0; e < n; ++e) {
+            if (R.gvec[st + e] == (int32_t)i) continue;
+            const double4 v = rec[st + e];
+            double s = f0 * v.x;
+            s = fma(f1, v.y, s);
+            const double cv = s / (nrm * v.z);
+            if (cv >= 1.0) continue;
+            best = fmax(best, cv);
+        }
+    };
+    scan(c);
+    int lo = c, hi = c, steps = 0;
+    bool full = false;
+    while (lo > 0 && !full) {
+        if (lo < c && line_bound(f0, f1, nrm, (double)lo / G + kLineEps, r) + kLineTau < best)
+            break;
+        scan(--lo);
+        full = ++steps > kLineWalk;
+    }
+    steps = 0;
+    while (hi < G - 1 && !full) {
+        if (hi > c && line_bound(f0, f1, nrm, (double)(hi + 1) / G - kLineEps, r) + kLineTau < best)
+            break;
+        scan(++hi);
+        full = ++steps > kLineWalk;
+    }
+    if (full) {
+        R.gtot[1] = 1;
+        return;
+    }
+    R.gamma[i] = best > -INFINITY ? acos(best < -1.0 ? -1.0 : best) : 1.5707963267948966;
+}
+
 // ------------------------------------------------------------- kernels
 __global__ __launch_bounds__(256) void k_grid_bucket(RunView R, int gate)
 {
@@ -949,6 +1007,10 @@ __global__ __launch_bounds__(64) void k_grid_cells(RunView R, int gate)
 }
 __global__ __launch_bounds__(256) void k_assoc_grid(RunView R) { assoc_grid_body(R, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_assoc_line(RunView R) { assoc_line_body(R, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_line_gamma(RunView R, int gate)
+{
+    line_gamma_body(R, blockIdx.x, gate);
+}
 
 // batched: blockIdx.x decoded into (run, local block) through the span
 // table; the build phases run for the runs whose vectors changed
@@ -979,6 +1041,11 @@ __global__ __launch_bounds__(256) void kb_assoc_line(const RunView *runs, const 
     const int s = find_span(sp, n, blockIdx.x);
     assoc_line_body(runs[sp[s].run], blockIdx.x - sp[s].start);
 }
+__global__ __launch_bounds__(256) void kb_line_gamma(const RunView *runs, const Span *sp, int n)
+{
+    const int s = find_span(sp, n, blockIdx.x);
+    line_gamma_body(runs[sp[s].run], blockIdx.x - sp[s].start, 0);
+}
 
 // ------------------------------------------------------------- launchers
 hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force)
@@ -989,7 +1056,10 @@ hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force)
     k_grid_bucket<<<vb, 256, 0, s>>>(R, force);
     k_grid_ranges<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(R, force);
     k_grid_fill<<<vb, 256, 0, s>>>(R, force);
-    if (R.m == 3) k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, force);
+    if (R.m == 3)
+        k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, force);
+    else
+        k_line_gamma<<<vb, 256, 0, s>>>(R, force);
     return hipGetLastError();
 }
 
@@ -1000,7 +1070,10 @@ hipError_t launch_grid_rebuild(const RunView &R, hipStream_t s)
     const int64_t cells = index_cells(R.m, R.gG);
     k_grid_ranges<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(R, 0);
     k_grid_fill<<<vb, 256, 0, s>>>(R, 0);
-    if (R.m == 3) k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, 0);
+    if (R.m == 3)
+        k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, 0);
+    else
+        k_line_gamma<<<vb, 256, 0, s>>>(R, 0);
     return hipGetLastError();
 }
 
@@ -1028,8 +1101,11 @@ hipError_t launch_batch_grid(int phase, int cls, const RunView *runs, const Span
         break;
     case BP_GRID_RANGES: kb_grid_ranges<<<g, 256, 0, s>>>(runs, sp, n); break;
     case BP_GRID_FILL: kb_grid_fill<<<g, 256, 0, s>>>(runs, sp, n); break;
-    case BP_GRID_CELLS:
-        kb_grid_cells<<<g, 64, 0, s>>>(runs, sp, n);
+    case BP_GRID_CELLS:  // class: the objective count (3: cells, 2: the line's gamma)
+        if (cls == 3)
+            kb_grid_cells<<<g, 64, 0, s>>>(runs, sp, n);
+        else
+            kb_line_gamma<<<g, 256, 0, s>>>(runs, sp, n);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -1044,7 +1120,7 @@ int64_t grid_phase_blocks(int phase, const RunView &R)
     case BP_ASSOC: return ((R.m == 3 ? R.M * kGridRowLanes : R.M) + 255) / 256;
     case BP_GRID_FILL: return (R.K + 255) / 256;
     case BP_GRID_RANGES: return (cells + 255) / 256;
-    case BP_GRID_CELLS: return R.m == 3 ? cells : 0;
+    case BP_GRID_CELLS: return R.m == 3 ? cells : (R.K + 255) / 256;
     }
     return 0;
 }

@@ -135,7 +135,7 @@ __device__ __forceinline__ void adapt_v_body(const RunView &R, int64_t bx, bool 
         R.gcell[j] = c;
         if (c >= 0) atomicAdd(&R.gcnt[c], 1);
         if (j == 0) {
-            R.gtot[1] = R.m == 3 ? 0 : 1;  // as the bucket pass sets them
+            R.gtot[1] = 0;  // as the bucket pass sets them
             R.gtot[2] = 0;
         }
     }
@@ -181,6 +181,7 @@ int batch_phase_class(int phase, const RunView &R)
         return offspring_segment(R.d, R.N) |
                (R.eta_c == 20.0 && R.eta_m == 20.0 ? kDefaultIndices : 0);
     if (phase == BP_ASSOC && R.gG > 0) return kIndexedClass | R.m;
+    if (phase == BP_GRID_CELLS) return R.m;  // the grid's cells, or the line's gamma
     if (phase == BP_ASSOC || phase == BP_RERANK || phase == BP_GAMMA_ASSOC ||
         phase == BP_GAMMA_RERANK)
         return R.m;

@@ -73,8 +73,8 @@ struct RunView {
     int32_t *lcnt;      // cells: candidate-list length (-1: full scan; grid only)
     int32_t *lstart;    // cells: first record of each list (-1: full scan; grid only)
     unsigned long long *gtot;  // 4: the allocator of the cells' vector ranges (build),
-                               // 1 when the build left some vector's gamma (always,
-                               // for the line), 1 when some vector is outside the
+                               // 1 when the build left some vector's gamma,
+                               // 1 when some vector is outside the
                                // line (every row then scans all vectors), spare
     double *lrec;       // gcap x 4: (v, |v|) of the list entries
     int32_t *lidx;      // gcap: vector id of each record
