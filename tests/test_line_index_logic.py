@@ -47,16 +47,23 @@ def build(V, r, G):
     return cells
 
 
-def walk(f, V, vn, r, G, cells):
+def walk(f, V, vn, r, G, cells, skip=None, nrm=None):
+    """The row walk; with skip = i it is the gamma walk of vector i (itself
+    and vectors at cosine 1 or more skipped, nrm = |v_i|)."""
     f0, f1 = f
-    nrm = np.sqrt(f0 * f0 + f1 * f1)
+    if nrm is None:
+        nrm = np.sqrt(f0 * f0 + f1 * f1)
     c = cell_of(f0, f1, r, G)
     best, bj = -np.inf, len(V)
 
     def scan(cc):
         nonlocal best, bj
         for j in cells[cc]:
+            if j == skip:
+                continue
             cv = cosine(f0, f1, nrm, V[j, 0], V[j, 1], vn[j])
+            if skip is not None and cv >= 1.0:
+                continue
             if cv > best or (cv == best and j < bj):
                 best, bj = cv, j
 
@@ -80,7 +87,7 @@ def walk(f, V, vn, r, G, cells):
         steps += 1
         if steps > WALK:
             return None
-    return bj
+    return bj if skip is None else best
 
 
 def brute(f, V, vn):
@@ -154,3 +161,24 @@ def test_walk_with_tiny_lines():
         V = lattice(H)
         rows = np.random.default_rng(H).random((100, 2))
         assert check(V, np.array([1.0, 1.0]), rows) == 0
+
+
+@pytest.mark.parametrize("scale", [(1.0, 1.0), (30.0, 0.2)], ids=["unit", "adapted"])
+def test_gamma_walk_finds_the_nearest_other_vector(scale):
+    """Eq. 5's gamma on the line: each vector walks as a row, skipping itself
+    and exactly parallel vectors; the largest cosine equals the brute-force
+    one over all other vectors (duplicates included in the set)."""
+    V = lattice(150) * np.array(scale)
+    V = np.concatenate([V, V[10:13]])  # exact duplicates
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    r = np.maximum(np.array(scale) / max(scale), 1e-6)
+    G = len(V)
+    vn = np.sqrt(V[:, 0] ** 2 + V[:, 1] ** 2)
+    cells = build(V, r, G)
+    for i in range(len(V)):
+        got = walk(V[i], V, vn, r, G, cells, skip=i, nrm=vn[i])
+        cv = np.array([cosine(V[i, 0], V[i, 1], vn[i], V[j, 0], V[j, 1], vn[j])
+                       for j in range(len(V))])
+        cv[i] = -np.inf
+        cv[cv >= 1.0] = -np.inf
+        assert got is not None and got == cv.max(), i
