@@ -505,10 +505,21 @@ __device__ float box_side_min(const RunView &R, int ci, int cj, int k, const F3 
     return lo;
 }
 
-// One wavefront per cell: the neighbourhood staged in LDS; b from the
-// cells within kNear; the box radius (lane k tests radius k, at most
-// kStage); the champions and the list from the staged box vectors, written
-// into the cell's slot at each lane's prefix.
+// The cells a row or a vector can land in: ci + cj <= G (cell_of clamps q
+// to the simplex, so floor(q1 G) + floor(q2 G) <= G); the others lie outside
+// it, hold no vector and are never read.  Row ci of them holds G cells for
+// ci <= 1 and G - ci + 1 after; t-th such cell in row order.
+__device__ __forceinline__ int64_t tri_start(int G, int ci)
+{
+    return ci == 0 ? 0 : (int64_t)G + (int64_t)(ci - 1) * (G + 1) - (int64_t)(ci - 1) * ci / 2;
+}
+static int64_t grid_live_cells(int G) { return (int64_t)G + (int64_t)G * (G + 1) / 2 - 1; }
+
+// One wavefront per cell (the simplex's cells only, in row order): the
+// neighbourhood staged in LDS; b from the cells within kNear; the box
+// radius (lane k tests radius k, at most kStage); the champions and the
+// list from the staged box vectors, written into the cell's slot at each
+// lane's prefix.
 // A neighbourhood over kStageCap vectors or a box over kStage marks the cell
 // for a full scan.  Also clears the cell's fill cursor and the range
 // allocator for the next build.
@@ -516,23 +527,21 @@ __device__ __forceinline__ void grid_cells_body(const RunView &R, int64_t bx, in
 {
     if (!gate && *R.vchanged == 0) return;
     const int G = R.gG;
-    const int c = (int)bx;
     const int lane = threadIdx.x;
-    if (c >= G * G) return;  // uniform
+    if (bx >= (int64_t)G + (int64_t)G * (G + 1) / 2 - 1) return;  // uniform
+    int ci = 0;  // the row of cell bx: the last row starting at or before it
+    for (int hi = G - 1; ci < hi;) {
+        const int mid = (ci + hi + 1) >> 1;
+        if (tri_start(G, mid) <= bx) ci = mid; else hi = mid - 1;
+    }
+    const int cj = (int)(bx - tri_start(G, ci));
+    const int c = ci * G + cj;
     __shared__ CellGeo g;
     __shared__ Champs ch;
     __shared__ Stage st;
-    const int ci = c / G, cj = c % G;
     if (lane == 0) {
         if (c == 0) R.gtot[0] = 0;
         R.gcnt[c] = 0;
-    }
-    if (ci + cj > G) {  // outside the simplex (corner sum above 1): no row lands here
-        if (lane == 0) {
-            R.lstart[c] = 0;
-            R.lcnt[c] = 0;
-        }
-        return;  // uniform
     }
     // stage: each lane's cells of the neighbourhood, their vector counts
     // scanned over the wave, then the vectors
@@ -1057,7 +1066,7 @@ hipError_t launch_grid_build(const RunView &R, hipStream_t s, int force)
     k_grid_ranges<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(R, force);
     k_grid_fill<<<vb, 256, 0, s>>>(R, force);
     if (R.m == 3)
-        k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, force);
+        k_grid_cells<<<(unsigned)grid_live_cells(R.gG), 64, 0, s>>>(R, force);
     else
         k_line_gamma<<<vb, 256, 0, s>>>(R, force);
     return hipGetLastError();
@@ -1071,7 +1080,7 @@ hipError_t launch_grid_rebuild(const RunView &R, hipStream_t s)
     k_grid_ranges<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(R, 0);
     k_grid_fill<<<vb, 256, 0, s>>>(R, 0);
     if (R.m == 3)
-        k_grid_cells<<<(unsigned)cells, 64, 0, s>>>(R, 0);
+        k_grid_cells<<<(unsigned)grid_live_cells(R.gG), 64, 0, s>>>(R, 0);
     else
         k_line_gamma<<<vb, 256, 0, s>>>(R, 0);
     return hipGetLastError();
@@ -1120,7 +1129,7 @@ int64_t grid_phase_blocks(int phase, const RunView &R)
     case BP_ASSOC: return ((R.m == 3 ? R.M * kGridRowLanes : R.M) + 255) / 256;
     case BP_GRID_FILL: return (R.K + 255) / 256;
     case BP_GRID_RANGES: return (cells + 255) / 256;
-    case BP_GRID_CELLS: return R.m == 3 ? cells : (R.K + 255) / 256;
+    case BP_GRID_CELLS: return R.m == 3 ? grid_live_cells(R.gG) : (R.K + 255) / 256;
     }
     return 0;
 }
