@@ -116,6 +116,46 @@ def test_batch_equals_alone(P, graphs):
         assert same(a, b) is None, same(a, b)
 
 
+def test_device_filling_batch_equals_alone(P):
+    """A batch whose full-scan runs fill the device by themselves (here
+    twenty-two 10,011-vector runs with the index switched off and two m = 5
+    runs: over 2,048 association workgroups with wide chunks, and over 8 x
+    2,048 gamma blocks) associates with wide vector chunks and gives the
+    gamma passes their own chunking and eight blocks per workgroup: every
+    run still ends bit-identical to the same run alone (own chunking),
+    adaptations included."""
+    G = 12  # an adaptation at generation 10
+    specs = [(1 + i % 3, 3, 12, 10011, 10011, 40 + i) for i in range(22)]
+    specs += [(2, 5, 30, 3876, 3876, 60), (3, 5, 20, 3000, 3060, 61)]
+
+    def build():
+        out = []
+        for pb, m, d, N, K, seed in specs:
+            r = P.Run(pb, m, d, N, K, seed=seed, params=P.default_params(t_max=100))
+            if m == 3:
+                r.set_index(False)
+            out.append(r)
+        return out
+
+    alone = build()
+    for r in alone:
+        r.run(G)
+    mixed = build()
+    batch = P.Batch(32)
+    for r in mixed:
+        batch.admit(r)
+    print("device-filling batch", flush=True)
+    batch.step(G)
+    batch.synchronize()
+    for a, b in zip(alone, mixed):
+        assert same(a, b) is None, same(a, b)
+    for r in mixed:
+        batch.retire(r)
+    batch.close()
+    for r in alone + mixed:
+        r.close()
+
+
 def test_staggered_join_and_leave(P):
     """Runs join at different generations, leave early, and the single-run
     path continues them afterwards."""
